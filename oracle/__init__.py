@@ -1,0 +1,31 @@
+"""Plain FP64 CPU oracle for the inverse matrix p-th root iteration.
+
+TEST INFRASTRUCTURE. Only the test suite, the package smoke check and the
+bench's CPU-baseline leg may import, call or execute anything in this package.
+The product (the HIP library and its Python binding) never uses it, and it
+shares no code with the product: no kernels, helpers, tables or constants. The
+only module both sides use is ``workloads`` (seeded input generators, which
+hold none of the method's arithmetic).
+
+Everything here is written for a reader to check against the paper by eye:
+NumPy float64, one library primitive per step (matmul, eigh), no blocking, no
+fusion, no reordering beyond what the cited passage states.
+
+Parity pins (tests marked "not gpu" check each of these):
+  * ``eig_root``       - against scipy.linalg.fractional_matrix_power, a
+                         hand-worked 2x2 closed form, diagonal closed form.
+  * ``solve``          - against eig_root, numpy.linalg.inv (p = 1), the
+                         scalar recursion on diagonal and scaled-identity A
+                         (bit for bit), spectral iteration counts, invariants.
+  * ``spectral_count`` - against the dense iteration's count.
+  * rounding emulator  - against torch dtype casts (bf16, fp16, fp8 e4m3).
+  * MLP forward/back   - backward against central finite differences; GELU
+                         against its closed form values.
+  * features           - against hand-computed values on small matrices.
+  * guard              - against dense sampling and the closed forms of the
+                         paper's eq. (3) start.
+Parity unpinned: none of the functions above lacks a pin. The accuracy the
+low-precision bulk phase reaches end to end has no value in the paper to
+compare with (its figures are not available); it is checked against this
+oracle's emulator only.
+"""

@@ -1,0 +1,236 @@
+"""FP64 oracle of the Bini-type iteration for A^{-1/p} (Section II, eqs. (1)-(3)).
+
+Test infrastructure only (see the package docstring).
+
+Notation follows Section II of the paper: A is symmetric positive definite,
+C_k the k-th iterate, p >= 1 the root. The update is eq. (1),
+    C_{k+1} = ((p + 1) C_k - C_k^{p+1} A) / p,
+convergent when the start satisfies eq. (2), ||I - C_0^p A||_2 < 1; the paper's
+start is eq. (3), C_0 = A^T / (||A||_1 ||A||_inf). For p = 1 the update is the
+Newton-Schulz iteration for the inverse (Section II).
+
+Readings of what the paper leaves open (each is listed in the design notes):
+  * evaluation order of C_k^{p+1} A: the default is the coupled form that
+    carries M_k = C_k^p A beside C_k, N_k = I + (I - M_k)/p,
+    C_{k+1} = C_k N_k, M_{k+1} = N_k^p M_k. In exact arithmetic it gives the same
+    iterates as eq. (1) (every factor is a polynomial in A, so they commute);
+    the literal right-multiplied order is kept as a diagnostic.
+  * start: eq. (3) ("paper"), or the scaled identity
+    C_0 = (||A||_1 ||A||_inf)^{-1/(2p)} I ("identity"), whose C_0^p A has its
+    spectrum in (0, 1] for every SPD A, so eq. (2) always holds.
+  * stopping: the Frobenius norm of I - M_k below tol, confirmed by the
+    directly computed ||I - C_k^p A||_F below tol.
+  * every iterate is symmetrised, X <- (X + X^T)/2.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+OK, EMAXITER, EFLOOR, EDIVERGED = 0, 2, 3, 4
+
+
+def norm_1(a: np.ndarray) -> float:
+    """||A||_1: the largest column sum of absolute values (eq. (3))."""
+    return float(np.max(np.sum(np.abs(a), axis=0)))
+
+
+def norm_inf(a: np.ndarray) -> float:
+    """||A||_inf: the largest row sum of absolute values (eq. (3))."""
+    return float(np.max(np.sum(np.abs(a), axis=1)))
+
+
+def sym(x: np.ndarray) -> np.ndarray:
+    return 0.5 * (x + x.T)
+
+
+def start_paper(a: np.ndarray, p: int) -> np.ndarray:
+    """Eq. (3): C_0 = A^T / (||A||_1 ||A||_inf)."""
+    return a.T / (norm_1(a) * norm_inf(a))
+
+
+def start_identity(a: np.ndarray, p: int) -> np.ndarray:
+    """Scaled identity C_0 = c I with c^p = (||A||_1 ||A||_inf)^{-1/2}.
+
+    ||A||_2 <= sqrt(||A||_1 ||A||_inf), so the eigenvalues of C_0^p A lie in
+    (0, 1] and eq. (2) holds for every SPD A."""
+    s = norm_1(a) * norm_inf(a)
+    return s ** (-1.0 / (2 * p)) * np.eye(a.shape[0])
+
+
+def start_poly(a: np.ndarray, p: int, b) -> np.ndarray:
+    """Polynomial start C_0 = sigma^{-1/p} (b0 I + b1 A/sigma + b2 (A/sigma)^2),
+    sigma = sqrt(||A||_1 ||A||_inf). b = (1, 0, 0) is the scaled identity."""
+    sigma = np.sqrt(norm_1(a) * norm_inf(a))
+    ah = a / sigma
+    n = a.shape[0]
+    q = b[0] * np.eye(n) + b[1] * ah + b[2] * (ah @ ah)
+    return sigma ** (-1.0 / p) * sym(q)
+
+
+def matpow(x: np.ndarray, p: int) -> np.ndarray:
+    out = x
+    for _ in range(p - 1):
+        out = out @ x
+    return out
+
+
+def true_residual(c: np.ndarray, a: np.ndarray, p: int) -> float:
+    """||I - C^p A||_F, computed from C and A directly."""
+    n = a.shape[0]
+    return float(np.linalg.norm(np.eye(n) - matpow(c, p) @ a))
+
+
+def eig_root(a: np.ndarray, p: int) -> np.ndarray:
+    """A^{-1/p} by definition: A = V diag(lam) V^T -> V diag(lam^{-1/p}) V^T."""
+    lam, v = np.linalg.eigh(a)
+    if np.any(lam <= 0):
+        raise ValueError("matrix is not positive definite")
+    return sym((v * lam ** (-1.0 / p)) @ v.T)
+
+
+def rel_fro(x: np.ndarray, ref: np.ndarray) -> float:
+    """Relative Frobenius error ||X - ref||_F / ||ref||_F (the paper's metric of
+    Section IV-C made relative)."""
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+@dataclass
+class Result:
+    c: np.ndarray
+    status: int
+    iters: int
+    rho: list = field(default_factory=list)     # ||I - M_k||_F per iteration
+    residual_true: float = float("nan")
+
+
+def _make_start(a, p, init, poly):
+    if isinstance(init, np.ndarray):
+        return init.copy()
+    if init == "paper":
+        return start_paper(a, p)
+    if init == "identity":
+        return start_identity(a, p)
+    if init == "poly":
+        return start_poly(a, p, poly)
+    raise ValueError(f"unknown start {init!r}")
+
+
+def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 100,
+          evaluation: str = "coupled", poly=(1.0, 0.0, 0.0),
+          floor_window: int = 3) -> Result:
+    """Run the iteration of eq. (1) until ||I - C^p A||_F < tol.
+
+    evaluation:
+      "coupled"        M_0 = C_0^p A; R = I - M; N = I + R/p; C <- C N;
+                       M <- N (N (... (N M))) (p products); both symmetrised.
+      "literal"        X = C^p A; C <- ((p + 1) C - C X) / p (eq. (1) as printed).
+      "newton_schulz"  p = 1 only: C <- C (2I - A C), symmetrised (Section II).
+
+    The returned iteration count is the number of updates applied. Status:
+    OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
+    1e6; EFLOOR when, once below 1, the residual has not fallen below half its
+    best value for ``floor_window`` consecutive iterations.
+    """
+    if not np.array_equal(a, a.T):
+        raise ValueError("A must be exactly symmetric")
+    if p < 1:
+        raise ValueError("p must be >= 1")
+    if evaluation == "newton_schulz" and p != 1:
+        raise ValueError("Newton-Schulz order is the p = 1 case")
+    n = a.shape[0]
+    eye = np.eye(n)
+    c = _make_start(a, p, init, poly)
+    m = matpow(c, p) @ a if evaluation == "coupled" else None
+    rhos = []
+    best = np.inf
+    stale = 0
+    for k in range(max_iter + 1):
+        if evaluation == "coupled":
+            r = eye - m
+        elif evaluation == "literal":
+            x = matpow(c, p) @ a
+            r = eye - x
+        else:
+            x = a @ c
+            r = eye - x
+        rho = float(np.linalg.norm(r))
+        rhos.append(rho)
+        if not np.isfinite(rho) or rho > 1e6:
+            return Result(c, EDIVERGED, k, rhos)
+        if rho < tol:
+            tau = true_residual(c, a, p)
+            if tau < tol:
+                return Result(c, OK, k, rhos, tau)
+        if rho < 1.0:
+            if rho < 0.5 * best:
+                best = rho
+                stale = 0
+            else:
+                stale += 1
+                if stale >= floor_window:
+                    return Result(c, EFLOOR, k, rhos, true_residual(c, a, p))
+        if k == max_iter:
+            break
+        if evaluation == "coupled":
+            nmat = eye + r / p
+            c = sym(c @ nmat)
+            for _ in range(p):
+                m = nmat @ m
+            m = sym(m)
+        elif evaluation == "literal":
+            c = ((p + 1) * c - c @ x) / p
+        else:
+            c = sym(c @ (2.0 * eye - x))
+    return Result(c, EMAXITER, max_iter, rhos, true_residual(c, a, p))
+
+
+def scalar_step(c, lam, p):
+    """Eq. (1) on one eigenvalue: c <- c (p + 1 - c^p lam) / p."""
+    return c * (p + 1 - c ** p * lam) / p
+
+
+def spectral_count(lam: np.ndarray, p: int, c0: np.ndarray, tol: float,
+                   max_iter: int = 200):
+    """Iteration count and residual trajectory of eq. (1) in exact arithmetic,
+    computed per eigenvalue: for A = V diag(lam) V^T and C_0 = V diag(c0) V^T the
+    iterates stay V diag(c_k) V^T, so ||I - C_k^p A||_F = sqrt(sum (1 - c^p lam)^2).
+
+    Returns (count, rho_list); count = max_iter + 1 when tol is not reached."""
+    c = np.asarray(c0, dtype=np.float64).copy()
+    rhos = []
+    for k in range(max_iter + 1):
+        rho = float(np.sqrt(np.sum((1.0 - c ** p * lam) ** 2)))
+        rhos.append(rho)
+        if rho < tol:
+            return k, rhos
+        if not np.isfinite(rho) or rho > 1e6:
+            return max_iter + 1, rhos
+        c = scalar_step(c, lam, p)
+    return max_iter + 1, rhos
+
+
+def spectral_start(lam: np.ndarray, p: int, init: str, sigma: float,
+                   poly=(1.0, 0.0, 0.0)) -> np.ndarray:
+    """Eigenvalues of C_0 for the starts above, given sigma = sqrt(||A||_1 ||A||_inf)
+    (for symmetric A, ||A||_1 = ||A||_inf, so sigma^2 = ||A||_1 ||A||_inf)."""
+    if init == "paper":
+        return lam / sigma ** 2
+    if init == "identity":
+        return np.full_like(lam, sigma ** (-1.0 / p))
+    if init == "poly":
+        x = lam / sigma
+        return sigma ** (-1.0 / p) * (poly[0] + poly[1] * x + poly[2] * x * x)
+    raise ValueError(init)
+
+
+def commutator(c: np.ndarray, a: np.ndarray) -> float:
+    """||CA - AC||_F / (||C||_F ||A||_F); zero for any function of A."""
+    return float(np.linalg.norm(c @ a - a @ c) / (np.linalg.norm(c) * np.linalg.norm(a)))
+
+
+def residual_map(r: np.ndarray, p: int) -> np.ndarray:
+    """Per-eigenvalue residual law of the coupled step: r = 1 - c^p lam maps to
+    1 - (1 - r)(1 + r/p)^p (the scalar form of M_{k+1} = N^p M)."""
+    return 1.0 - (1.0 - r) * (1.0 + r / p) ** p

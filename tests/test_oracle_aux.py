@@ -1,0 +1,120 @@
+"""Pins of the oracle's rounding emulator, MLP reference, features and guard."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import features as ft
+from oracle import guard, mlp, rounding
+
+
+@pytest.mark.parametrize("fmt,dtype", [("bf16", torch.bfloat16), ("fp16", torch.float16),
+                                       ("fp8_e4m3", torch.float8_e4m3fn)])
+def test_round_to_format_matches_torch_casts(fmt, dtype):
+    rng = np.random.default_rng(0)
+    vmax = rounding.FORMATS[fmt][2]
+    x = rng.standard_normal(20000).astype(np.float32) * np.float32(4.0) ** rng.integers(-8, 5, 20000)
+    x = x[np.abs(x) < 0.9 * vmax].astype(np.float32)
+    ref = torch.from_numpy(x).to(dtype).to(torch.float64).numpy()
+    got = rounding.round_to_format(x.astype(np.float64), fmt)
+    assert np.array_equal(got, ref)
+
+
+def test_custom_10_bits_is_half_precision_in_range():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1000, 1000, 5000)
+    x = x[np.abs(x) > 2.0 ** -14]
+    assert np.array_equal(rounding.round_custom(x, 10), rounding.round_to_format(x, "fp16"))
+
+
+def test_round_half_to_even():
+    # 1 + 2^-8 is halfway between two bf16 neighbours: ties go to the even one (1.0)
+    assert rounding.round_to_format(np.array([1 + 2.0 ** -8]), "bf16")[0] == 1.0
+    assert rounding.round_to_format(np.array([1 + 3 * 2.0 ** -8]), "bf16")[0] == 1 + 2.0 ** -6
+
+
+def test_tile_scaling_roundtrip_and_exponents():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((300, 260)) * 1e-5
+    x[:128, :128] *= 1e6
+    codes, ex = rounding.quantize(x, "fp8_e4m3", 128)
+    assert ex.shape == (3, 3)
+    # largest magnitude of each tile lands in [2^7, 2^8) before rounding
+    for bi in range(3):
+        for bj in range(3):
+            blk = codes[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128]
+            assert 2 ** 7 <= np.max(np.abs(blk)) <= 2 ** 8
+    back = rounding.dequantize(codes, ex, 128)
+    rel = np.abs(back - x) / np.maximum(np.abs(x), 1e-300)
+    big = np.abs(x) > 2.0 ** -6 * np.ldexp(1.0, np.repeat(np.repeat(ex, 128, 0), 128, 1)[:300, :260] + 7)
+    assert np.all(rel[big] <= 2.0 ** -4)
+
+
+def test_gelu_known_values():
+    # GELU(x) = x Phi(x); Phi(1) = 0.8413447460685429 (standard normal table)
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15
+    assert abs(mlp.gelu(np.array([-1.0]))[0] + (1 - 0.8413447460685429)) < 1e-15
+    h = 1e-6
+    x = np.linspace(-3, 3, 13)
+    fd = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_grad(x), fd, atol=1e-8)
+
+
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    nparam = mlp.n_params()
+    assert nparam == 16 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+    theta = rng.standard_normal(nparam) * 0.2
+    x = rng.standard_normal((7, 16))
+    t = rng.standard_normal((7, 3))
+    g, _ = mlp.backward(theta, x, t)
+    idx = rng.choice(nparam, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(nparam); e[i] = h
+        lp = mlp.loss(mlp.forward(theta + e, x)[0], t)
+        lm = mlp.loss(mlp.forward(theta - e, x)[0], t)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-5 * abs(fd), i
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([0.3, -2.0, 1e-3])
+    th, m, v = mlp.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    # bias-corrected first step: -lr * g / (|g| + eps)
+    assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_features_on_hand_matrix():
+    a = np.array([[4.0, -1.0, 0.0], [-1.0, 3.0, 1.0], [0.0, 1.0, 2.0]])
+    f = ft.features(a, 2)
+    sigma = 5.0                       # ||A||_1 = ||A||_inf = 5
+    b = a / sigma
+    assert f.shape == (16,)
+    assert f[0] == math.log2(3) / 10 and f[1] == 0.5
+    assert abs(f[2] - 9.0 / 5 / 3) < 1e-15                       # trace/sigma/n
+    assert abs(f[3] - (16 + 9 + 4 + 4 * 1) / 25 / 3) < 1e-15      # ||B||_F^2 / n
+    assert abs(f[7] - 0.4) < 1e-15 and abs(f[8] - 0.8) < 1e-15
+    assert abs(f[10] - min(0.8 - 0.2, 0.6 - 0.4, 0.4 - 0.2)) < 1e-15
+    assert abs(f[11] - (5 + 5 + 3) / 5 / 3) < 1e-15
+    assert abs(f[12] - (1 + 2 + 1) / 9) < 1e-15
+    assert abs(f[13] - 0.2) < 1e-15
+    assert abs(f[15] - math.log10(5)) < 1e-15
+    assert abs(f[14] - np.std([0.8, 0.6, 0.4]) / 0.6) < 1e-15
+
+
+def test_guard_identity_and_paper_starts():
+    # scaled identity: phi(x) = x on (0,1] -> accepted, sup 1
+    ok, sup, qmin = guard.check((1.0, 0.0, 0.0), 2)
+    assert ok and abs(sup - 1.0) < 1e-12
+    # eq. (3) start is C_0 = A/sigma^2 -> q(x) = sigma^{1/p - 1} x, phi = sigma^{1-p} x^{p+1}
+    for sigma, p, expect in ((0.1, 2, False), (3.0, 2, True), (0.5, 3, False), (1.0, 1, True)):
+        b = (0.0, sigma ** (1.0 / p - 1.0), 0.0)
+        ok, sup, _ = guard.check(b, p)
+        assert ok == expect and abs(sup - sigma ** (1 - p)) < 1e-9
+    # a start whose phi overshoots 2 is rejected
+    assert not guard.check((2.0, 0.0, 0.0), 1)[0]
+    assert not guard.check((1.0, -2.0, 0.0), 2)[0]
