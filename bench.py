@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Time to ||I - C^p A||_F < 1e-10 for one n = 16384, p = 2 SPD matrix on one MI355X.
+
+One step = one complete solve through the C ABI (ipr_solve): the norms and
+start of eq. (3)'s family, every iteration of eq. (1), and the final check of
+the residual from C and A. A is already resident in HBM when timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line. Besides the headline schedule (FP64, scaled-identity
+start, triangle products) it times, outside the timed steps, the comparators:
+plain FP64 with full products, the eq. (3) start, and low-precision bulk
+phases; and the oracle on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (vendor figure)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("gemm_f64.hip", "kernels_common.h"):
+        with open(os.path.join(ROOT, "paper_1703_02283_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n):
+    """HBM bytes per launch of the FP64 product from the committed counter
+    summary, when it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "gemm_f64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("n") != n:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p, tol, kappa, seed, iters_ref):
+    """The oracle on the host cores, on a bounded sample: one coupled
+    iteration (with its start and final check: 7 FP64 products for p = 2) at
+    n = 8192, scaled by flops to the n = 16384 solve."""
+    from threadpoolctl import threadpool_info
+    import numpy as np
+    import workloads as w
+    from oracle import iteration as it
+    n_s = 8192
+    a, _ = w.householder_spd(n_s, kappa, seed=seed)
+    t0 = time.perf_counter()
+    it.solve(a, p, tol, max_iter=1)
+    dt = time.perf_counter() - t0
+    prods_sample = p + (p + 1) + p          # M_0, one iteration, final check
+    prods_full = p + (p + 1) * iters_ref + p
+    scale = (16384 / n_s) ** 3 * prods_full / prods_sample
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    return {"value": dt * scale, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle.iteration.solve (coupled form, identity start) on householder_spd "
+                      f"n={n_s} kappa={kappa:g}, max_iter=1 = {prods_sample} FP64 products in "
+                      f"{dt:.2f} s, scaled by flops to {prods_full} products at n=16384 "
+                      f"({iters_ref} iterations)",
+            "host_cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1703_02283_amd as ipr
+    import workloads as w
+
+    ipr.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n, p, tol = args.n, args.p, args.tol
+
+    log(f"building householder_spd n={n} kappa={args.kappa:g} seed={args.seed}")
+    t0 = time.time()
+    a_host, lam = w.householder_spd(n, args.kappa, seed=args.seed)
+    log(f"  built in {time.time() - t0:.1f} s")
+    A = torch.from_numpy(a_host).to(dev)
+    del a_host
+    C = torch.empty_like(A)
+    sched = ipr.ipr_schedule_default(timing=1)
+    ws = torch.empty(ipr.ipr_workspace_size(n, p, 1, sched), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def solve(s):
+        _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, workspace=ws, stream=stream)
+        return r
+
+    for i in range(args.warmup):
+        r = solve(sched)
+        log(f"warmup {i}: status {r.status} iters {r.iters_fp64} residual {r.residual_true:.3e}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [solve(sched) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, r in enumerate(results):
+        log(f"step {i}: status {r.status} iters {r.iters_fp64} residual {r.residual_true:.3e} "
+            f"gemms {r.gemms} ms_gemm {r.ms_gemm:.1f}")
+    ok = all(r.status == ipr.IPR_OK for r in results)
+    sec = elapsed / max(1, args.steps)
+    g_ms = sum(r.ms_gemm for r in results)
+    g_fl = sum(r.gemm_flops for r in results)
+    g_n = sum(r.gemm_launches for r in results)
+    achieved = g_fl / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None
+    last = results[-1]
+
+    out = {
+        "metric": "time to ||I-C^pA||_F<1e-10, n=16384 p=2: mixed/learned vs FP64; MFMA TFLOP/s",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"householder_spd n={n} p={p} kappa={args.kappa:g} "
+                               f"seed={args.seed} tol={tol:g}",
+                   "n": n, "p": p, "kappa": args.kappa, "tol": tol,
+                   "schedule": "fp64, scaled-identity start, triangle products"},
+        "solve": {"status_all_ok": ok, "iterations": last.iters_fp64, "gemms": last.gemms,
+                  "residual_true": last.residual_true, "ms_norms": last.ms_norms,
+                  "ms_init": last.ms_init, "ms_refine": last.ms_refine,
+                  "ms_verify": last.ms_verify},
+        "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
+                     "traffic": traffic_from_profile(n),
+                     "launches": g_n, "avg_launch_ms": g_ms / g_n if g_n else None,
+                     "flops_per_launch": g_fl / g_n if g_n else None},
+    }
+
+    comps = {}
+    if not args.no_comparators:
+        def run(name, **kw):
+            s = ipr.ipr_schedule_default(timing=1, **kw)
+            need = ipr.ipr_workspace_size(n, p, 1, s)
+            wsx = ws if need <= ws.numel() else torch.empty(need, dtype=torch.uint8, device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, workspace=wsx, stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            d = {"seconds": dt, "status": ipr.binding.STATUS_NAMES[r.status],
+                 "iters_bulk": r.iters_bulk, "iters_fp64": r.iters_fp64, "gemms": r.gemms,
+                 "residual_true": r.residual_true,
+                 "fp64_tflops": (r.gemm_flops / (r.ms_gemm * 1e-3) / 1e12) if r.ms_gemm else None}
+            log(name, json.dumps(d))
+            comps[name] = d
+            return d
+
+        run("fp64_identity_full_products", triangle=0)
+        # eq. (3) start: it cannot reach 1e-10 in FP64 at this condition number;
+        # run a bounded number of iterations and model the time of the
+        # exact-arithmetic count from the measured time per iteration.
+        d = run("fp64_paper_eq3_full_products_12_iterations", triangle=0,
+                init=ipr.IPR_INIT_PAPER_EQ3, max_iter=12)
+        try:
+            gold = json.load(open(os.path.join(ROOT, "tests", "golden", "iteration_counts.json")))
+            key = f"householder_n16384_kappa{args.kappa:g}_seed{args.seed}"
+            k_eq3 = gold["counts"][key][f"p{p}"]["paper"]
+            k_id = gold["counts"][key][f"p{p}"]["identity"]
+        except Exception:
+            k_eq3 = k_id = None
+        if k_eq3 and d["iters_fp64"]:
+            per_it = d["seconds"] / d["iters_fp64"]
+            comps["fp64_paper_eq3_modelled"] = {
+                "seconds": per_it * k_eq3, "iterations_exact_arithmetic": k_eq3,
+                "note": "measured time per full-product iteration x exact-arithmetic count; "
+                        "in FP64 this start floors above 1e-10 (about u kappa^(p+1))"}
+            out["speedup_vs_paper_eq3_modelled"] = per_it * k_eq3 / sec
+        comps["iterations_identity_exact_arithmetic"] = k_id
+        fi = comps["fp64_identity_full_products"]
+        out["speedup_vs_fp64_full_products"] = fi["seconds"] / sec
+        for name, dt in (("fp16", ipr.IPR_FP16), ("fp8_e4m3", ipr.IPR_FP8_E4M3),
+                         ("bf16", ipr.IPR_BF16)):
+            run(f"mixed_{name}_bulk_then_fp64", bulk_dtype=dt)
+    out["comparators"] = comps
+
+    if not args.no_cpu:
+        try:
+            k_ref = comps.get("iterations_identity_exact_arithmetic") or last.iters_fp64
+            out["cpu_baseline"] = cpu_baseline(p, tol, args.kappa, args.seed, int(k_ref))
+        except Exception as e:  # report, never hide
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

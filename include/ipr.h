@@ -1,0 +1,182 @@
+/*
+ * libipr: inverse matrix p-th roots A^{-1/p} of symmetric positive definite
+ * matrices on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the iteration of Bini et al. as stated in Section II of
+ * Lass, Kuehne, Plessl, "Using Approximate Computing for the Calculation of
+ * Inverse Matrix p-th Roots" (arXiv 1703.02283):
+ *   eq. (1)  C_{k+1} = ((p + 1) C_k - C_k^{p+1} A) / p,
+ *   eq. (2)  convergence when ||I - C_0^p A||_2 < 1,
+ *   eq. (3)  the start C_0 = A^T / (||A||_1 ||A||_inf).
+ * For p = 1 the iteration is the Newton-Schulz iteration for A^{-1}.
+ *
+ * Conventions shared by every entry point below:
+ *   - Matrices are dense, n x n, row-major with leading dimension n, float64
+ *     unless stated. A must be exactly symmetric; symmetry and definiteness
+ *     are not checked (an indefinite A shows up as IPR_EDIVERGED).
+ *   - Pointers named d* are device pointers owned by the caller. The library
+ *     never allocates or frees device memory: all temporary storage comes from
+ *     the caller's workspace (see ipr_workspace_size). The only memory the
+ *     library allocates is a small pinned host buffer per calling thread, used
+ *     to read one scalar per iteration; it lives until the process ends.
+ *   - All device work is ordered on `stream`. Calls that return host results
+ *     synchronise the stream before returning; ipr_solve also synchronises once
+ *     per iteration to read the residual.
+ *   - A workspace must not be shared by calls that may overlap in time.
+ *   - Every function returns an ipr_status; on IPR_EHIP or IPR_EARG,
+ *     ipr_last_error() returns a message for the calling thread.
+ */
+#ifndef IPR_H
+#define IPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IPR_OK = 0,
+  IPR_EARG = 1,        /* invalid argument or workspace too small */
+  IPR_EMAXITER = 2,    /* max_iter updates applied without reaching tol */
+  IPR_EFLOOR = 3,      /* the residual stopped falling above tol (precision floor) */
+  IPR_EDIVERGED = 4,   /* NaN/Inf or residual > 1e6 */
+  IPR_EHIP = 5,        /* a HIP runtime call failed */
+  IPR_EGUARD = 6       /* a requested start violates eq. (2) and fallback was disabled */
+} ipr_status;
+
+/* Start C_0 (Section II). */
+typedef enum {
+  IPR_INIT_IDENTITY = 0,  /* C_0 = (||A||_1 ||A||_inf)^{-1/(2p)} I: satisfies eq. (2) for every SPD A */
+  IPR_INIT_PAPER_EQ3 = 1, /* eq. (3): C_0 = A^T / (||A||_1 ||A||_inf) */
+  IPR_INIT_POLY = 2,      /* C_0 = s^{-1/p} (b0 I + b1 A/s + b2 (A/s)^2), s = sqrt(||A||_1 ||A||_inf) */
+  IPR_INIT_LEARNED = 3    /* POLY with (b0, b1, b2) predicted by the MLP in schedule.mlp_params */
+} ipr_init;
+
+/* Arithmetic type of the bulk (early) iterations. FP64 refinement follows a
+ * low-precision bulk phase (Section III: low precision first, precise last). */
+typedef enum {
+  IPR_FP64 = 0,
+  IPR_BF16 = 1,      /* bf16 operands, fp32 accumulation */
+  IPR_FP16 = 2,      /* fp16 operands with per-128x128-tile power-of-two scales, fp32 accumulation */
+  IPR_FP8_E4M3 = 3   /* fp8 e4m3 operands with per-128x128-tile power-of-two scales, fp32 accumulation */
+} ipr_dtype;
+
+typedef struct {
+  int init;            /* ipr_init */
+  int bulk_dtype;      /* ipr_dtype */
+  int max_iter;        /* cap on updates (default 100) */
+  int triangle;        /* 1: compute one triangle of every symmetric product and mirror it (default 1) */
+  int guard_fallback;  /* 1: a POLY/LEARNED/PAPER_EQ3 start that fails the eq. (2) check falls back to IDENTITY (default 1) */
+  int verify;          /* 1: confirm ||I - C^p A||_F < tol from C and A before returning OK (default 1) */
+  double bulk_switch;  /* low-precision bulk phase ends when its residual falls below this or stalls (default 0.05) */
+  double stall_ratio;  /* "stalled" = residual not below stall_ratio * best for 2 iterations (default 0.5) */
+  double poly[3];      /* b0, b1, b2 for IPR_INIT_POLY */
+  const float* mlp_params; /* device, IPR_MLP_NPARAM floats, for IPR_INIT_LEARNED */
+  int timing;          /* 1: time every matrix product with device events (ms_gemm, gemm_flops) */
+} ipr_schedule;
+
+typedef struct {
+  int status;          /* ipr_status of the solve */
+  int iters_bulk;      /* updates applied in the low-precision bulk phase */
+  int iters_fp64;      /* updates applied in FP64 */
+  int fallback_used;   /* 1 if the requested start failed the guard and IDENTITY was used */
+  int gemms;           /* matrix products launched (all phases) */
+  double residual_proxy; /* last tracked ||I - C^p A||_F */
+  double residual_true;  /* ||I - C^p A||_F computed from C and A (NaN if not verified) */
+  double init_bound;   /* sup over x in (0,1] of q(x)^p x for the start used (eq. (2) needs < 2) */
+  double norm1, norminf; /* ||A||_1 and ||A||_inf */
+  double poly_used[3]; /* (b0, b1, b2) of the start used, in the POLY parametrisation */
+  double ms_norms, ms_init, ms_bulk, ms_refine, ms_verify; /* phase times (device events) */
+  int gemm_launches;   /* products timed (schedule.timing = 1) */
+  double ms_gemm;      /* their summed device time */
+  double gemm_flops;   /* their algorithmic flops: 2 n^3 per full product, n^2 (n + 1) per triangle */
+} ipr_result;
+
+#define IPR_MLP_NIN 16
+#define IPR_MLP_NHID 64
+#define IPR_MLP_NOUT 3
+/* W1 (64x16), b1 (64), W2 (64x64), b2 (64), W3 (3x64), b3 (3), row-major. */
+#define IPR_MLP_NPARAM (IPR_MLP_NHID * IPR_MLP_NIN + IPR_MLP_NHID + IPR_MLP_NHID * IPR_MLP_NHID + \
+                        IPR_MLP_NHID + IPR_MLP_NOUT * IPR_MLP_NHID + IPR_MLP_NOUT)
+
+/* Fills *s with the defaults documented above (IDENTITY start, FP64, triangle on). */
+void ipr_schedule_default(ipr_schedule* s);
+
+/* Bytes of device workspace a solve of order <= n_max and root <= p_max needs
+ * (batch = 1), or a batched solve of `batch` matrices whose orders sum their
+ * squares to at most n_max * n_max (see ipr_solve_batched). */
+size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s);
+
+/* A^{-1/p} of one SPD matrix (Section II, eqs. (1)-(3)).
+ *   dA    device, n x n float64, symmetric (read only)
+ *   dC    device, n x n float64: receives A^{-1/p} (exactly symmetric)
+ *   tol   stop when ||I - C^p A||_F < tol (> 0)
+ *   s     schedule (NULL = defaults)
+ *   out   host, receives the result record (may be NULL)
+ *   dWork device workspace of work_bytes >= ipr_workspace_size(n, p, 1, s)
+ * Returns IPR_OK when the residual was reached; IPR_EFLOOR / IPR_EMAXITER /
+ * IPR_EDIVERGED leave the last iterate in dC. */
+int ipr_solve(const double* dA, double* dC, int n, int p, double tol,
+              const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
+              hipStream_t stream);
+
+/* Independent solves of `batch` SPD matrices of uneven orders in one
+ * persistent kernel launch (device-side iteration loop per matrix).
+ *   dA_packed, dC_packed  device, matrices back to back (float64)
+ *   offsets  host, batch int64: element offset of matrix i in both buffers
+ *   n, p     host, batch ints: order (1 <= n <= 1024) and root (1 <= p <= 8)
+ *   out      host, batch result records (may be NULL)
+ * Only IPR_INIT_IDENTITY and IPR_FP64 / IPR_BF16 bulk are supported here. */
+int ipr_solve_batched(const double* dA_packed, double* dC_packed, const int64_t* offsets,
+                      const int* n, const int* p, int batch, double tol,
+                      const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
+                      hipStream_t stream);
+
+/* D = L^T R for n x n float64 matrices on the FP64 matrix cores (the product
+ * every step of eq. (1) is made of), followed by D <- alpha D + beta X + gamma I.
+ * X may be NULL. With triangle = 1 only the upper triangle is computed and
+ * mirrored (for products known to be symmetric). dD must not alias dL or dR. */
+int ipr_gemm(const double* dL, const double* dR, const double* dX, double* dD, int n,
+             double alpha, double beta, double gamma, int triangle, hipStream_t stream);
+
+/* Low-precision product (the storage-approximation regime of Sections III-B
+ * and IV): L and R are rounded to `dtype` with per-128x128-tile power-of-two
+ * scales (fp16, fp8) or none (bf16), multiplied on the matrix cores with fp32
+ * accumulation; D (float64) = L^T R. dWork >= ipr_gemm_lowp_workspace(n). */
+int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype,
+                  void* dWork, size_t work_bytes, hipStream_t stream);
+size_t ipr_gemm_lowp_workspace(int n);
+
+/* ||A||_1 and ||A||_inf (eq. (3)) into host out[0], out[1]. dWork >= n*(n/256+2)*8 bytes. */
+int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
+              hipStream_t stream);
+
+/* 16 features of each matrix of a packed batch (the learned start's input):
+ * dFeat (device, batch x 16 float32). Definitions: see the feature table in
+ * the design notes; all are O(n^2). offsets/n/p are host arrays. */
+int ipr_features(const double* dA_packed, const int64_t* offsets, const int* n, const int* p,
+                 int batch, float* dFeat, void* dWork, size_t work_bytes, hipStream_t stream);
+
+/* MLP 16 -> 64 -> 64 -> 3 with GELU (float32): dY (batch x 3) from dX (batch x 16). */
+int ipr_mlp_forward(const float* dParams, const float* dX, float* dY, int batch,
+                    hipStream_t stream);
+
+/* One training step on a mini-batch: mean squared error against dT (batch x 3),
+ * gradient into dGrad (IPR_MLP_NPARAM), then an Adam update of dParams with
+ * moments dM, dV (IPR_MLP_NPARAM each) at step `step` (1-based). The batch
+ * loss is written to *dLoss (device float). dWork >= ipr_mlp_workspace(batch). */
+int ipr_mlp_train_step(float* dParams, float* dGrad, float* dM, float* dV, const float* dX,
+                       const float* dT, int batch, int step, float lr, float* dLoss,
+                       void* dWork, size_t work_bytes, hipStream_t stream);
+size_t ipr_mlp_workspace(int batch);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* ipr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPR_H */

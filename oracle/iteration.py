@@ -90,6 +90,15 @@ def eig_root(a: np.ndarray, p: int) -> np.ndarray:
     return sym((v * lam ** (-1.0 / p)) @ v.T)
 
 
+def householder_root(n: int, kappa: float, seed: int, p: int) -> np.ndarray:
+    """A^{-1/p} by definition for the ``workloads.householder_spd`` matrix of the
+    same arguments: its eigenvectors are H's columns and its eigenvalues are
+    known, so A^{-1/p} = H diag(lam^{-1/p}) H^T (built in O(n^2 k))."""
+    import workloads
+    lam, vmat, t = workloads.householder_factors(n, kappa, seed)
+    return workloads.householder_congruence(vmat, t, lam ** (-1.0 / p))
+
+
 def rel_fro(x: np.ndarray, ref: np.ndarray) -> float:
     """Relative Frobenius error ||X - ref||_F / ||ref||_F (the paper's metric of
     Section IV-C made relative)."""

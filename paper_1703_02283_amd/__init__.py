@@ -1,0 +1,17 @@
+"""MI355X-native inverse matrix p-th roots (Bini-type iteration, Section II of
+Lass, Kuehne, Plessl, arXiv 1703.02283).
+
+The work is done by libipr.so (HIP kernels for gfx950 behind a C ABI,
+declared in include/ipr.h). This package is a thin ctypes binding whose
+functions carry the C names; torch supplies device memory and streams only.
+There is no CPU fallback: if the library is not built, every call raises.
+"""
+from .binding import (  # noqa: F401
+    IPR_OK, IPR_EARG, IPR_EMAXITER, IPR_EFLOOR, IPR_EDIVERGED, IPR_EHIP, IPR_EGUARD,
+    IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED,
+    IPR_FP64, IPR_BF16, IPR_FP16, IPR_FP8_E4M3, IPR_MLP_NPARAM,
+    IprSchedule, IprResult, IprError, library_path, load,
+    ipr_schedule_default, ipr_workspace_size, ipr_solve, ipr_solve_batched, ipr_gemm,
+    ipr_gemm_lowp, ipr_gemm_lowp_workspace, ipr_norms, ipr_features, ipr_mlp_forward,
+    ipr_mlp_train_step, ipr_mlp_workspace, ipr_last_error,
+)

@@ -1,0 +1,56 @@
+// C ABI of the low-precision product (ipr_gemm_lowp).
+#include <hip/hip_runtime.h>
+
+#include "../../include/ipr.h"
+#include "ipr_host.h"
+#include "lowp.h"
+
+using namespace ipr;
+
+namespace {
+struct LpWork {
+  void* lq;
+  void* rq;
+  int* el;
+  int* er;
+};
+size_t lp_work(int n, int dtype, LpWork* w, void* base, size_t cap, bool* ok) {
+  Carver c(base, cap);
+  w->lq = c.take<uint8_t>(lp_bytes(n, dtype));
+  w->rq = c.take<uint8_t>(lp_bytes(n, dtype));
+  w->el = c.take<int>(lp_exp_count(n));
+  w->er = c.take<int>(lp_exp_count(n));
+  *ok = c.ok();
+  return c.used;
+}
+}  // namespace
+
+extern "C" {
+
+size_t ipr_gemm_lowp_workspace(int n) {
+  if (n < 1) return 0;
+  LpWork w;
+  bool ok;
+  return lp_work(n, LP_FP16, &w, nullptr, (size_t)-1, &ok) + 256;
+}
+
+int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype, void* dWork,
+                  size_t work_bytes, hipStream_t stream) {
+  g_last_error.clear();
+  if (!dL || !dR || !dD || !dWork || n < 1) return fail(IPR_EARG, "ipr_gemm_lowp: bad argument");
+  if (dtype != IPR_BF16 && dtype != IPR_FP16 && dtype != IPR_FP8_E4M3)
+    return fail(IPR_EARG, "ipr_gemm_lowp: dtype must be BF16, FP16 or FP8_E4M3");
+  if (dD == dL || dD == dR) return fail(IPR_EARG, "ipr_gemm_lowp: output aliases an operand");
+  LpWork w;
+  bool ok;
+  lp_work(n, dtype, &w, dWork, work_bytes, &ok);
+  if (!ok) return fail(IPR_EARG, "ipr_gemm_lowp: workspace too small");
+  HIP_TRY(quantize_t(dL, n, dtype, w.lq, w.el, stream));
+  HIP_TRY(quantize_t(dR, n, dtype, w.rq, w.er, stream));
+  Epilogue e;
+  e.D = dD;
+  HIP_TRY(gemm_lp(w.lq, w.el, w.rq, w.er, n, dtype, 0, e, stream));
+  return IPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// FP64 matrix-core product D = L^T R with a fused affine epilogue.
+//
+// Every step of the iteration of eq. (1) (Section II) is a dense n x n x n
+// product followed by an elementwise update; this kernel is that step.
+//
+// Design for gfx950:
+//  * 128 x 128 output tile per workgroup of 4 wave64s (2 x 2), each wave owning
+//    64 x 64 = 4 x 4 blocks of v_mfma_f64_16x16x4f64.
+//  * The left operand is read as L^T: for D = L^T R both operands stream rows
+//    k of L and R, 128 contiguous doubles (1 KiB) per row and tile, so every
+//    global load is a fully coalesced row segment and neither operand needs a
+//    transpose on its way into LDS. Every left operand of the iteration is
+//    symmetric, so L^T R = L R there.
+//  * K slabs of 16 double-buffered in LDS (one barrier per slab); the row pitch
+//    of 144 doubles puts consecutive k rows half a bank sweep apart, so the
+//    16-lane row reads of the MFMA operands are conflict free.
+//  * XCD-aware tile order: workgroup w runs on XCD w % 8, so w is remapped to
+//    give each XCD a contiguous run of 8 x 8-tile super-tiles, whose 16 row and
+//    column panels then stay in that XCD's L2 while its 64 tiles are in flight.
+//  * Triangle mode computes only tiles on or above the diagonal and mirrors
+//    them: every product of the iteration is a polynomial in A, hence
+//    symmetric, so this halves the work and keeps every iterate symmetric.
+#include "kernels_common.h"
+
+namespace ipr {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;        // tile edge (rows = cols)
+constexpr int BK = 16;         // k slab per LDS stage
+constexpr int WT = 64;         // wave tile edge
+constexpr int LDP = BM + 16;   // LDS row pitch in doubles
+constexpr int NT = 256;        // threads per workgroup
+
+__global__ __launch_bounds__(NT, 2)
+void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R, int n,
+                     Grid gr, int tri, Epilogue e) {
+  __shared__ double Ls[2][BK][LDP];
+  __shared__ double Rs[2][BK][LDP];
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lw = logical_wg();
+  int bi, bj;
+  if (!tile_of(lw, gr, tri, &bi, &bj)) {
+    if (e.partial && tid == 0) e.partial[lw] = 0.0;
+    return;
+  }
+
+  const int i0 = bi * BM, j0 = bj * BM;
+  const int wm0 = (wave >> 1) * WT, wn0 = (wave & 1) * WT;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  // Loader: 16 rows x 128 columns per operand = 1024 double2; thread t moves
+  // rows (t / 64) + 4q, q = 0..3, columns 2 (t % 64) and 2 (t % 64) + 1.
+  const int lrow = tid >> 6;
+  const int lcol = (tid & 63) * 2;
+  const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
+  double2 la[4], ra[4];
+
+  auto gload = [&](int k0) {
+    if (cols_in && k0 + BK <= n) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t row = (size_t)(k0 + lrow + 4 * q) * n;
+        la[q] = *reinterpret_cast<const double2*>(L + row + i0 + lcol);
+        ra[q] = *reinterpret_cast<const double2*>(R + row + j0 + lcol);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + lrow + 4 * q;
+        const size_t row = (size_t)k * n;
+        const bool kin = k < n;
+        la[q].x = (kin && i0 + lcol < n) ? L[row + i0 + lcol] : 0.0;
+        la[q].y = (kin && i0 + lcol + 1 < n) ? L[row + i0 + lcol + 1] : 0.0;
+        ra[q].x = (kin && j0 + lcol < n) ? R[row + j0 + lcol] : 0.0;
+        ra[q].y = (kin && j0 + lcol + 1 < n) ? R[row + j0 + lcol + 1] : 0.0;
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<double2*>(&Ls[buf][lrow + 4 * q][lcol]) = la[q];
+      *reinterpret_cast<double2*>(&Rs[buf][lrow + 4 * q][lcol]) = ra[q];
+    }
+  };
+
+  const int nk = (n + BK - 1) / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+
+  const int fr = lane >> 4;   // k row of this lane's operand element
+  const int fc = lane & 15;   // m (or n) index of this lane's operand element
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = Ls[buf][kk + fr][wm0 + a * 16 + fc];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Rs[buf][kk + fr][wn0 + b * 16 + fc];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue. Output element r of block (a, b) in this lane (the f64 16x16x4
+  // layout, checked on gfx950): row lane / 16 + 4 r, column lane % 16.
+  double psum = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        epilogue_element(e, n, tri, i0 + wm0 + a * 16 + fr + 4 * r, j0 + wn0 + b * 16 + fc,
+                         acc[a][b][r], psum);
+  if (e.partial) store_partial(e.partial, lw, psum, red);
+}
+
+}  // namespace
+
+int gemm_partial_slots(int n, int tri) { return make_grid(n, tri, BM).nwg; }
+
+hipError_t gemm_f64(const double* L, const double* R, int n, int tri, const Epilogue& e,
+                    hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (!L || !R) return hipErrorInvalidValue;  // never launch on a missing operand
+  Grid gr = make_grid(n, tri, BM);
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3(gr.nwg), dim3(NT), 0, stream, L, R, n, gr, tri, e);
+  return hipGetLastError();
+}
+
+}  // namespace ipr

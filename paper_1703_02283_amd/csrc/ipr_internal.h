@@ -1,0 +1,64 @@
+// Internal declarations shared by the HIP translation units of libipr.
+// Not part of the public C ABI (include/ipr.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace ipr {
+
+// Affine epilogue applied to each output element (i, j) of a product
+// acc = L^T R:
+//   out = alpha * acc + beta * X[i,j] + gamma * (i == j)
+//   D[i,j] = out                                   (when D != nullptr)
+//   S[i,j] = (s_init ? sa*(i==j) + sb*Y[i,j] : S[i,j]) + sc*out   (when S != nullptr)
+//   partial[tile] = sum of (out - pd*(i==j))^2 over the tile (when partial != nullptr)
+// In triangle mode only tiles with row-block <= column-block are computed;
+// every element with i <= j is written to (i, j) and (j, i), and the partial
+// sums count off-diagonal elements twice, so they are sums over the full matrix.
+struct Epilogue {
+  double alpha = 1.0;
+  double beta = 0.0;
+  const double* X = nullptr;
+  double gamma = 0.0;
+  double* D = nullptr;
+  double* S = nullptr;
+  const double* Y = nullptr;
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  int s_init = 0;
+  double* partial = nullptr;
+  double pd = 0.0;
+};
+
+// Number of per-tile partial slots a product of order n writes.
+int gemm_partial_slots(int n, int tri);
+
+// D = L^T R (n x n, row-major, leading dimension n) in FP64 on the matrix
+// cores, with the epilogue above. L^T R equals L R whenever L is symmetric,
+// which holds for every left operand of the iteration.
+hipError_t gemm_f64(const double* L, const double* R, int n, int tri,
+                    const Epilogue& e, hipStream_t stream);
+
+// sqrt(sum of slots[0..count)) into *out (device), fixed summation order.
+hipError_t reduce_fro(const double* slots, int count, double* out, hipStream_t stream);
+
+// Column and row sums of |A|; writes norm1 = max column sum and
+// norminf = max row sum to out[0], out[1] (device). scratch holds n doubles.
+hipError_t norms_1_inf(const double* A, int n, double* scratch, double* out,
+                       hipStream_t stream);
+
+// C = c I, M = cp A and N = ((p+1) I - M) / p, with per-row partial sums of
+// (I - M)^2 in partial[0..n).
+hipError_t init_identity(const double* A, int n, int p, double c, double cp, double* C,
+                         double* M, double* N, double* partial, hipStream_t stream);
+
+// Y = a * X + b * I (elementwise over an n x n matrix).
+hipError_t affine(const double* X, int n, double a, double b, double* Y,
+                  hipStream_t stream);
+
+hipError_t copy(const double* X, size_t count, double* Y, hipStream_t stream);
+
+// X <- (X + X^T) / 2 in place.
+hipError_t symmetrize(double* X, int n, hipStream_t stream);
+
+}  // namespace ipr

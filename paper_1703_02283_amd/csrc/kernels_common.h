@@ -1,0 +1,95 @@
+// Device-side pieces shared by the product kernels: the XCD-aware tile order
+// and the affine epilogue of ipr::Epilogue.
+#pragma once
+#include "ipr_internal.h"
+
+namespace ipr {
+
+struct Grid {
+  int nt;     // tiles per edge
+  int g;      // super-tile edge in tiles
+  int s;      // super-tiles per edge
+  int ntot;   // logical workgroups (super-tiles * g * g)
+  int nwg;    // launched workgroups (ntot rounded up to a multiple of 8)
+};
+
+inline Grid make_grid(int n, int tri, int tile) {
+  Grid gr;
+  gr.nt = (n + tile - 1) / tile;
+  gr.g = gr.nt < 8 ? gr.nt : 8;
+  gr.s = (gr.nt + gr.g - 1) / gr.g;
+  const int nsuper = tri ? gr.s * (gr.s + 1) / 2 : gr.s * gr.s;
+  gr.ntot = nsuper * gr.g * gr.g;
+  gr.nwg = (gr.ntot + 7) / 8 * 8;
+  return gr;
+}
+
+// Workgroup w is dispatched to XCD w % 8. The logical index gives each XCD a
+// contiguous run of g x g-tile super-tiles (column-major inside a super-tile),
+// so the row and column panels of the tiles an XCD has in flight share its L2.
+// In triangle mode super-tiles enumerate the upper triangle row by row.
+__device__ __forceinline__ int logical_wg() {
+  const int per = gridDim.x >> 3;
+  return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+__device__ __forceinline__ bool tile_of(int lw, const Grid& gr, int tri, int* bi, int* bj) {
+  if (lw >= gr.ntot) return false;
+  const int gg = gr.g * gr.g;
+  const int u = lw / gg, loc = lw - u * gg;
+  int si, sj;
+  if (tri) {
+    int r = 0, base = 0;
+    while (base + (gr.s - r) <= u) {
+      base += gr.s - r;
+      ++r;
+    }
+    si = r;
+    sj = r + (u - base);
+  } else {
+    si = u / gr.s;
+    sj = u - si * gr.s;
+  }
+  *bi = si * gr.g + loc % gr.g;
+  *bj = sj * gr.g + loc / gr.g;
+  return *bi < gr.nt && *bj < gr.nt && (!tri || *bi <= *bj);
+}
+
+// Applies the epilogue to element (i, j) whose product value is acc; adds its
+// contribution to the Frobenius partial sum.
+__device__ __forceinline__ void epilogue_element(const Epilogue& e, int n, int tri, int i, int j,
+                                                 double acc, double& psum) {
+  if (i >= n || j >= n) return;
+  if (tri && i > j) return;
+  const size_t ij = (size_t)i * n + j;
+  const size_t ji = (size_t)j * n + i;
+  const bool mirror = tri && i != j;
+  double v = e.alpha * acc;
+  if (e.X) v += e.beta * e.X[ij];
+  if (i == j) v += e.gamma;
+  if (e.D) {
+    e.D[ij] = v;
+    if (mirror) e.D[ji] = v;
+  }
+  if (e.S) {
+    double s = e.s_init ? ((i == j ? e.sa : 0.0) + (e.Y ? e.sb * e.Y[ij] : 0.0)) : e.S[ij];
+    s += e.sc * v;
+    e.S[ij] = s;
+    if (mirror) e.S[ji] = s;
+  }
+  const double q = (i == j) ? v - e.pd : v;
+  psum += mirror ? 2.0 * q * q : q * q;
+}
+
+// Sum over the workgroup of 4 wave64s into e.partial[slot] (fixed order).
+__device__ __forceinline__ void store_partial(double* partial, int slot, double psum,
+                                              double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) psum += __shfl_xor(psum, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = psum;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[slot] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+}  // namespace ipr

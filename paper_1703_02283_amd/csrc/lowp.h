@@ -1,0 +1,23 @@
+// Low-precision operand storage and products (lowp.hip).
+#pragma once
+#include "ipr_internal.h"
+
+namespace ipr {
+
+// Same codes as ipr_dtype.
+enum { LP_BF16 = 1, LP_FP16 = 2, LP_FP8 = 3 };
+
+int lp_padded(int n);              // n rounded up to a multiple of 128
+int lp_esize(int dtype);           // bytes per code
+size_t lp_bytes(int n, int dtype); // bytes of one padded code matrix
+size_t lp_exp_count(int n);        // ints of one tile-exponent array
+int lp_partial_slots(int n, int tri);
+
+// Q (padded, transposed) and E (per-tile exponents) from X (n x n float64).
+hipError_t quantize_t(const double* X, int n, int dtype, void* Q, int* E, hipStream_t stream);
+
+// D = L^T R from quantized operands (fp32 accumulation) with the float64 epilogue.
+hipError_t gemm_lp(const void* Lq, const int* EL, const void* Rq, const int* ER, int n,
+                   int dtype, int tri, const Epilogue& e, hipStream_t stream);
+
+}  // namespace ipr

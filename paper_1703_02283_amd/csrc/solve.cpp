@@ -1,0 +1,673 @@
+// Host driver of libipr: argument checks, workspace carving, the starts of
+// Section II and the iteration loop of eq. (1), built from the kernels of
+// gemm_f64.hip and elementwise.hip.
+//
+// Evaluation of eq. (1). In exact arithmetic every iterate is a polynomial in
+// A, so eq. (1) can carry M_k = C_k^p A beside C_k (the coupled form):
+//   N_k = I + (I - M_k) / p,  C_{k+1} = C_k N_k,  M_{k+1} = N_k^p M_k,
+// and C_{k+1} equals ((p + 1) C_k - C_k^{p+1} A) / p. This ordering is stable
+// (the right-multiplied order of eq. (1) amplifies rounding errors that do
+// not commute with A), costs p + 1 products per iteration and yields the
+// residual I - M_k for free. The last product of each iteration also writes
+// N_{k+1} and the Frobenius partial sums of I - M_{k+1} in its epilogue.
+// For p = 1 after a low-precision phase the Newton-Schulz order
+// R_k = I - A C_k, C_{k+1} = C_k + C_k R_k is used instead: it recomputes the
+// residual from A and so removes errors of any kind.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/ipr.h"
+#include "ipr_host.h"
+#include "ipr_internal.h"
+#include "lowp.h"
+
+namespace ipr {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static double* pinned_scalars() {
+  thread_local double* buf = nullptr;
+  if (!buf) {
+    if (hipHostMalloc((void**)&buf, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      buf = nullptr;
+  }
+  return buf;
+}
+
+int read_scalars(const double* d, int count, double* host, hipStream_t stream) {
+  double* pin = pinned_scalars();
+  if (!pin) return fail(IPR_EHIP, "hipHostMalloc of the scalar buffer failed");
+  HIP_TRY(hipMemcpyAsync(pin, d, count * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (int i = 0; i < count; ++i) host[i] = pin[i];
+  return IPR_OK;
+}
+
+void poly_guard(const double b[3], int p, double* sup_phi, int* q_pos) {
+  auto q = [&](double x) { return b[0] + b[1] * x + b[2] * x * x; };
+  auto phi = [&](double x) { return std::pow(q(x), p) * x; };
+  // sup of q^p x on [0, 1]: at x = 1 or at a root of
+  // d/dx (q^p x) / q^(p-1) = (2p+1) b2 x^2 + (p+1) b1 x + b0 in (0, 1).
+  double s = phi(1.0);
+  const double aa = (2.0 * p + 1.0) * b[2], bb = (p + 1.0) * b[1], cc = b[0];
+  if (aa != 0.0) {
+    const double disc = bb * bb - 4 * aa * cc;
+    if (disc >= 0) {
+      const double sq = std::sqrt(disc);
+      for (double x : {(-bb + sq) / (2 * aa), (-bb - sq) / (2 * aa)})
+        if (x > 0.0 && x < 1.0) s = std::max(s, phi(x));
+    }
+  } else if (bb != 0.0) {
+    const double x = -cc / bb;
+    if (x > 0.0 && x < 1.0) s = std::max(s, phi(x));
+  }
+  // q > 0 on (0, 1]
+  int pos;
+  if (b[0] == 0.0) {
+    // q = x (b1 + b2 x): positive on (0, 1] iff b1 > 0 and b1 + b2 > 0 ... and
+    // b1 + b2 x > 0 on (0, 1], i.e. at both ends of the linear factor
+    pos = (b[1] > 0.0 && b[1] + b[2] > 0.0) ? 1 : 0;
+  } else {
+    double mq = std::min(q(0.0), q(1.0));
+    if (b[2] != 0.0) {
+      const double xv = -b[1] / (2 * b[2]);
+      if (xv > 0.0 && xv < 1.0) mq = std::min(mq, q(xv));
+    }
+    pos = mq > 0.0 ? 1 : 0;
+  }
+  *sup_phi = s;
+  *q_pos = pos;
+}
+
+}  // namespace ipr
+
+using namespace ipr;
+
+namespace {
+
+constexpr int NMAT = 7;     // float64 n x n work matrices
+constexpr int NLP = 6;      // quantized operand slots (low-precision phase)
+
+struct Work {
+  double* m[NMAT];
+  double* partial;
+  double* norms_scratch;
+  double* scal;
+  void* lq[NLP];
+  int* le[NLP];
+};
+
+int n_mats(int p) { return p == 1 ? 5 : (p == 2 ? 6 : NMAT); }
+
+size_t carve(int n, int p, int dtype, Work* w, void* base, size_t cap, bool* ok) {
+  Carver c(base, cap);
+  const size_t nn = (size_t)n * n;
+  const int nm = n_mats(p);
+  for (int i = 0; i < NMAT; ++i) w->m[i] = i < nm ? c.take<double>(nn) : nullptr;
+  const size_t slots =
+      std::max<size_t>(std::max(gemm_partial_slots(n, 0), gemm_partial_slots(n, 1)), n);
+  w->partial = c.take<double>(slots);
+  const size_t strips = (n + 255) / 256;
+  w->norms_scratch = c.take<double>(2 * (size_t)n + strips * n);
+  w->scal = c.take<double>(64);
+  for (int i = 0; i < NLP; ++i) {
+    const bool lp = dtype != IPR_FP64;
+    w->lq[i] = lp ? (void*)c.take<uint8_t>(lp_bytes(n, dtype)) : nullptr;
+    w->le[i] = lp ? c.take<int>(lp_exp_count(n)) : nullptr;
+  }
+  *ok = c.ok();
+  return c.used;
+}
+
+struct Timer {
+  hipEvent_t ev[8];
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    for (auto& e : ev) (void)hipEventCreate(&e);
+  }
+  ~Timer() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  void mark(int i) { (void)hipEventRecord(ev[i], s); }
+  double ms(int a, int b) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+    return t;
+  }
+};
+
+// Products of one solve. In the low-precision phase every operand is read
+// through a small cache of quantized copies; a float64 matrix that a product
+// or an elementwise kernel rewrites loses its cached copy.
+struct Prod {
+  int n;
+  hipStream_t st;
+  int lowp_dtype = 0;  // 0: FP64 products
+  Work* w;
+  int gemms = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs of timed products
+  std::vector<double> flops;
+  const double* src[NLP] = {};
+  bool valid[NLP] = {};
+  unsigned long use[NLP] = {};
+  unsigned long clock = 0;
+
+  void invalidate(const double* X) {
+    for (int i = 0; i < NLP; ++i)
+      if (src[i] == X) valid[i] = false;
+  }
+  int slot_for(const double* X, int keep, hipError_t* err) {
+    for (int i = 0; i < NLP; ++i)
+      if (valid[i] && src[i] == X) {
+        use[i] = ++clock;
+        return i;
+      }
+    int v = -1;  // a free slot, else the least recently used one (never `keep`)
+    for (int i = 0; i < NLP && v < 0; ++i)
+      if (i != keep && !valid[i]) v = i;
+    if (v < 0)
+      for (int i = 0; i < NLP; ++i)
+        if (i != keep && (v < 0 || use[i] < use[v])) v = i;
+    *err = quantize_t(X, n, lowp_dtype, w->lq[v], w->le[v], st);
+    src[v] = X;
+    valid[v] = true;
+    use[v] = ++clock;
+    return v;
+  }
+  ~Prod() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  // a product in FP64 whatever the phase
+  hipError_t f64(const double* L, const double* R, int tri, const Epilogue& e) {
+    const int keep = lowp_dtype;
+    lowp_dtype = 0;
+    hipError_t err = (*this)(L, R, tri, e);
+    lowp_dtype = keep;
+    return err;
+  }
+  hipError_t operator()(const double* L, const double* R, int tri, const Epilogue& e) {
+    hipError_t err = hipSuccess;
+    ++gemms;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing && !lowp_dtype) {
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hipErrorOutOfMemory;
+      ev.push_back(e0);
+      ev.push_back(e1);
+      flops.push_back(tri ? (double)n * n * (n + 1.0) : 2.0 * n * n * (double)n);
+      (void)hipEventRecord(e0, st);
+    }
+    if (!lowp_dtype) {
+      err = gemm_f64(L, R, n, tri, e, st);
+    } else {
+      const int a = slot_for(L, -1, &err);
+      if (err != hipSuccess) return err;
+      const int b = slot_for(R, a, &err);
+      if (err != hipSuccess) return err;
+      err = gemm_lp(w->lq[a], w->le[a], w->lq[b], w->le[b], n, lowp_dtype, tri, e, st);
+    }
+    if (e1) (void)hipEventRecord(e1, st);
+    if (e.D) invalidate(e.D);
+    if (e.S) invalidate(e.S);
+    return err;
+  }
+  int slots(int tri) const { return gemm_partial_slots(n, tri); }
+  // after the stream has drained
+  void totals(int* count, double* ms, double* fl) const {
+    *count = (int)flops.size();
+    *ms = 0.0;
+    *fl = 0.0;
+    for (size_t i = 0; i < flops.size(); ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) *ms += t;
+      *fl += flops[i];
+    }
+  }
+};
+
+#define TRY(expr)                       \
+  do {                                  \
+    hipError_t _e = (expr);             \
+    if (_e != hipSuccess)               \
+      return fail(IPR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+struct Solver {
+  const double* A;
+  int n, p, tri;
+  hipStream_t st;
+  Work w;
+  Prod prod;
+  double* Cb[2];
+  int ci = 0;
+  double* Mb[2];
+  int mi = 0;
+  double* Nb[2];
+  int ni = 0;
+  double* X[2] = {nullptr, nullptr};
+  double* Rns = nullptr;  // Newton-Schulz residual (p = 1 after a low-precision phase)
+  int slots = 0;          // partial slots holding the current residual's sum of squares
+
+  double* C() { return Cb[ci]; }
+  double* M() { return Mb[mi]; }
+  double* rho_dev() { return w.scal + 8; }
+
+  int reduce() {
+    TRY(reduce_fro(w.partial, slots, rho_dev(), st));
+    return IPR_OK;
+  }
+
+  // Epilogue of the product that yields M: writes M, N = ((p+1) I - M) / p and
+  // the partial sums of (I - M)^2.
+  Epilogue m_epilogue(double* Mout, double* Nout) {
+    Epilogue e;
+    e.D = Mout;
+    e.S = Nout;
+    e.s_init = 1;
+    e.sa = (p + 1.0) / p;
+    e.sc = -1.0 / p;
+    e.partial = w.partial;
+    e.pd = 1.0;
+    return e;
+  }
+
+  // Mout = L^p B (p products, last with m_epilogue), t = triangle mode.
+  int power_chain(const double* L, const double* B, double* Mout, double* Nout, int t) {
+    const double* src = B;
+    for (int j = 1; j <= p; ++j) {
+      Epilogue e;
+      if (j == p)
+        e = m_epilogue(Mout, Nout);
+      else
+        e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
+      TRY(prod(L, src, t, e));
+      src = e.D;
+    }
+    if (!t) {
+      TRY(symmetrize(Mout, n, st));
+      TRY(symmetrize(Nout, n, st));
+      prod.invalidate(Mout);
+      prod.invalidate(Nout);
+    }
+    slots = prod.slots(t);
+    return reduce();
+  }
+
+  // One update of eq. (1); leaves the residual's partial sums in w.partial.
+  int step(bool ns) {
+    double* Cc = C();
+    double* Cn = Cb[ci ^ 1];
+    if (ns) {
+      Epilogue e;  // C_{k+1} = C_k + C_k R_k (symmetric: C_k - C_k A C_k + C_k)
+      e.beta = 1.0;
+      e.X = Cc;
+      e.D = Cn;
+      TRY(prod(Cc, Rns, tri, e));
+      if (!tri) TRY(symmetrize(Cn, n, st));
+      prod.invalidate(Cn);
+      // R_{k+1} = I - A C_{k+1}, full product: mirroring it would symmetrise the
+      // residual, and C + C sym(I - A C) is not self-correcting (an error E that
+      // does not commute with A is multiplied by (1 - lambda_j / lambda_i) / 2).
+      Epilogue e2;
+      e2.alpha = -1.0;
+      e2.gamma = 1.0;
+      e2.D = Rns;
+      e2.partial = w.partial;
+      TRY(prod(A, Cn, 0, e2));
+      slots = prod.slots(0);
+      ci ^= 1;
+      return reduce();
+    }
+    double* Nc = Nb[ni];
+    {
+      Epilogue e;  // C_{k+1} = C_k N_k
+      e.D = Cn;
+      TRY(prod(Cc, Nc, tri, e));
+      if (!tri) TRY(symmetrize(Cn, n, st));
+      prod.invalidate(Cn);
+    }
+    // M_{k+1} = N_k (N_k (... (N_k M_k))), N_{k+1} from M_{k+1}
+    if (int rc = power_chain(Nc, M(), Mb[mi ^ 1], Nb[ni ^ 1], tri)) return rc;
+    ci ^= 1;
+    mi ^= 1;
+    ni ^= 1;
+    return IPR_OK;
+  }
+
+  // ||I - C^p A||_F from p full products into *tau (host).
+  int true_residual(double* tau) {
+    const double* src = A;
+    for (int j = 1; j <= p; ++j) {
+      Epilogue e;
+      if (j == p) {
+        e.alpha = -1.0;
+        e.gamma = 1.0;
+        e.partial = w.partial;
+      } else {
+        e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
+      }
+      TRY(prod.f64(C(), src, 0, e));
+      src = e.D;
+    }
+    TRY(reduce_fro(w.partial, gemm_partial_slots(n, 0), w.scal + 9, st));
+    return read_scalars(w.scal + 9, 1, tau, st);
+  }
+
+  // M_k = C_k^p A (and N_k) from C_k, or R_k = I - A C_k in Newton-Schulz mode.
+  int recompute(bool ns) {
+    if (ns) {
+      Epilogue e;
+      e.alpha = -1.0;
+      e.gamma = 1.0;
+      e.D = Rns;
+      e.partial = w.partial;
+      TRY(prod(A, C(), 0, e));
+      slots = prod.slots(0);
+      return reduce();
+    }
+    return power_chain(C(), A, M(), Nb[ni], 0);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void ipr_schedule_default(ipr_schedule* s) {
+  if (!s) return;
+  std::memset(s, 0, sizeof *s);
+  s->init = IPR_INIT_IDENTITY;
+  s->bulk_dtype = IPR_FP64;
+  s->max_iter = 100;
+  s->triangle = 1;
+  s->guard_fallback = 1;
+  s->verify = 1;
+  s->bulk_switch = 0.05;
+  s->stall_ratio = 0.5;
+  s->poly[0] = 1.0;
+}
+
+const char* ipr_last_error(void) { return g_last_error.c_str(); }
+
+size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s) {
+  if (n_max < 1 || p_max < 1 || batch < 1) return 0;
+  Work w;
+  bool ok;
+  const int dt = s ? s->bulk_dtype : IPR_FP64;
+  return carve(n_max, p_max, dt, &w, nullptr, (size_t)-1, &ok) + 256;
+}
+
+int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
+              hipStream_t stream) {
+  g_last_error.clear();
+  if (!dA || !out || !dWork || n < 1) return fail(IPR_EARG, "ipr_norms: bad argument");
+  Carver c(dWork, work_bytes);
+  const size_t strips = (n + 255) / 256;
+  double* scratch = c.take<double>(2 * (size_t)n + strips * n);
+  double* res = c.take<double>(2);
+  if (!c.ok())
+    return fail(IPR_EARG, "ipr_norms: workspace too small (%zu < %zu)", work_bytes, c.used);
+  HIP_TRY(norms_1_inf(dA, n, scratch, res, stream));
+  return read_scalars(res, 2, out, stream);
+}
+
+int ipr_gemm(const double* dL, const double* dR, const double* dX, double* dD, int n,
+             double alpha, double beta, double gamma, int triangle, hipStream_t stream) {
+  g_last_error.clear();
+  if (!dL || !dR || !dD || n < 1) return fail(IPR_EARG, "ipr_gemm: bad argument");
+  if (dD == dL || dD == dR) return fail(IPR_EARG, "ipr_gemm: output aliases an operand");
+  Epilogue e;
+  e.alpha = alpha;
+  e.beta = dX ? beta : 0.0;
+  e.X = dX;
+  e.gamma = gamma;
+  e.D = dD;
+  HIP_TRY(gemm_f64(dL, dR, n, triangle ? 1 : 0, e, stream));
+  return IPR_OK;
+}
+
+int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_schedule* sched,
+              ipr_result* out, void* dWork, size_t work_bytes, hipStream_t stream) {
+  g_last_error.clear();
+  ipr_schedule sd;
+  ipr_schedule_default(&sd);
+  const ipr_schedule& s = sched ? *sched : sd;
+  ipr_result res;
+  std::memset(&res, 0, sizeof res);
+  res.residual_true = std::numeric_limits<double>::quiet_NaN();
+  if (!dA || !dC || !dWork) return fail(IPR_EARG, "ipr_solve: null pointer");
+  if (n < 1 || p < 1 || p > 64) return fail(IPR_EARG, "ipr_solve: need n >= 1 and 1 <= p <= 64");
+  if (!(tol > 0.0)) return fail(IPR_EARG, "ipr_solve: tol must be > 0");
+  if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve: max_iter < 0");
+  if (s.init < IPR_INIT_IDENTITY || s.init > IPR_INIT_LEARNED)
+    return fail(IPR_EARG, "ipr_solve: unknown init %d", s.init);
+  if (s.bulk_dtype < IPR_FP64 || s.bulk_dtype > IPR_FP8_E4M3)
+    return fail(IPR_EARG, "ipr_solve: unknown bulk dtype %d", s.bulk_dtype);
+  if (s.init == IPR_INIT_LEARNED)
+    return fail(IPR_EARG, "ipr_solve: learned start is not available in this build");
+
+  Solver sv;
+  bool ok;
+  carve(n, p, s.bulk_dtype, &sv.w, dWork, work_bytes, &ok);
+  if (!ok)
+    return fail(IPR_EARG, "ipr_solve: workspace too small (%zu bytes, need %zu)", work_bytes,
+                ipr_workspace_size(n, p, 1, sched));
+  sv.A = dA;
+  sv.n = n;
+  sv.p = p;
+  sv.tri = s.triangle ? 1 : 0;
+  sv.st = stream;
+  sv.prod.n = n;
+  sv.prod.st = stream;
+  sv.prod.w = &sv.w;
+  sv.prod.timing = s.timing != 0;
+  Work& w = sv.w;
+  sv.Cb[0] = dC;
+  sv.Cb[1] = w.m[0];
+  sv.Mb[0] = w.m[1];
+  sv.Mb[1] = w.m[2];
+  sv.Nb[0] = w.m[3];
+  sv.Nb[1] = w.m[4];
+  sv.X[0] = p >= 2 ? w.m[5] : nullptr;
+  sv.X[1] = p >= 3 ? w.m[6] : nullptr;
+  sv.Rns = w.m[2];  // Newton-Schulz (p = 1) does not carry M
+  const size_t nn = (size_t)n * n;
+  Timer tm(stream);
+
+  // ---- norms of eq. (3)
+  tm.mark(0);
+  HIP_TRY(norms_1_inf(dA, n, w.norms_scratch, w.scal, stream));
+  double nrm[2];
+  if (int rc = read_scalars(w.scal, 2, nrm, stream)) return rc;
+  res.norm1 = nrm[0];
+  res.norminf = nrm[1];
+  const double s2 = nrm[0] * nrm[1];
+  const double sigma = std::sqrt(s2);
+  tm.mark(1);
+  if (!(s2 > 0.0) || !std::isfinite(s2))
+    return fail(IPR_EARG, "ipr_solve: A has zero or non-finite norm");
+
+  // ---- start C_0 (as sigma^{-1/p} q(A/sigma)) and R_0 = I - C_0^p A
+  double b[3] = {1.0, 0.0, 0.0};
+  int init = s.init;
+  if (init == IPR_INIT_POLY) {
+    for (int i = 0; i < 3; ++i) b[i] = s.poly[i];
+  } else if (init == IPR_INIT_PAPER_EQ3) {
+    // A / sigma^2 = sigma^{-1/p} q(A / sigma) with q(x) = sigma^{1/p - 1} x
+    b[0] = 0.0;
+    b[1] = std::pow(sigma, 1.0 / p - 1.0);
+  }
+  double sup_phi;
+  int q_pos;
+  poly_guard(b, p, &sup_phi, &q_pos);
+  if (!(q_pos && sup_phi < 2.0)) {
+    if (!s.guard_fallback)
+      return fail(IPR_EGUARD, "ipr_solve: start violates eq. (2) (sup q^p x = %g)", sup_phi);
+    res.fallback_used = 1;
+    init = IPR_INIT_IDENTITY;
+    b[0] = 1.0;
+    b[1] = b[2] = 0.0;
+    poly_guard(b, p, &sup_phi, &q_pos);
+  }
+  res.init_bound = sup_phi;
+  for (int i = 0; i < 3; ++i) res.poly_used[i] = b[i];
+
+  const double root = std::pow(sigma, -1.0 / p);
+  if (init == IPR_INIT_IDENTITY) {
+    HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(), sv.M(),
+                          sv.Nb[sv.ni], w.partial, stream));
+    sv.slots = n;
+    if (int rc = sv.reduce()) return rc;
+  } else {
+    if (b[2] != 0.0) {
+      Epilogue e;
+      e.alpha = root * b[2] / s2;
+      e.beta = root * b[1] / sigma;
+      e.X = dA;
+      e.gamma = root * b[0];
+      e.D = sv.C();
+      HIP_TRY(sv.prod(dA, dA, sv.tri, e));
+      if (!sv.tri) HIP_TRY(symmetrize(sv.C(), n, stream));
+    } else {
+      HIP_TRY(affine(dA, n, root * b[1] / sigma, root * b[0], sv.C(), stream));
+    }
+    // M_0 = C_0^p A: products of polynomials in A, symmetric
+    if (int rc = sv.power_chain(sv.C(), dA, sv.M(), sv.Nb[sv.ni], sv.tri)) return rc;
+  }
+  tm.mark(2);
+
+  // ---- iterations: optional low-precision bulk phase, then FP64
+  const bool lowp = s.bulk_dtype != IPR_FP64;
+  bool lp_restart = false;
+  int status = IPR_EMAXITER;
+  int k = 0, kb = 0;
+  double rho = 0.0;
+  if (lowp) {
+    sv.prod.lowp_dtype = s.bulk_dtype;
+    if (p == 1)  // Newton-Schulz bulk: R_0 = I - A C_0
+      if (int rc = sv.recompute(true)) return rc;
+    double best = std::numeric_limits<double>::infinity();
+    int stale = 0;
+    for (kb = 0; kb < s.max_iter; ++kb) {
+      if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
+      if (!std::isfinite(rho) || rho > 1e6) break;
+      if (rho < s.bulk_switch) break;
+      if (rho < 1.0) {
+        if (rho < s.stall_ratio * best) {
+          best = rho;
+          stale = 0;
+        } else if (++stale >= 2) {
+          break;
+        }
+      }
+      if (int rc = sv.step(p == 1)) return rc;
+    }
+    sv.prod.lowp_dtype = 0;
+    res.iters_bulk = kb;
+    if (!std::isfinite(rho) || rho > 1e6) {
+      // the low-precision phase diverged: start again in FP64 from the scaled identity
+      res.fallback_used = 1;
+      lp_restart = true;
+      sv.ci = sv.mi = sv.ni = 0;
+      HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(),
+                            sv.M(), sv.Nb[sv.ni], w.partial, stream));
+      sv.slots = n;
+      if (int rc = sv.reduce()) return rc;
+    } else {
+      if (int rc = sv.recompute(p == 1)) return rc;
+    }
+  }
+  tm.mark(3);
+  // Newton-Schulz order for p = 1 once a low-precision phase has run
+  const bool ns = lowp && p == 1 && !lp_restart;
+  double best = std::numeric_limits<double>::infinity();
+  int stale = 0, failed_verify = 0, verified_at = -1;
+  double last_tau = std::numeric_limits<double>::infinity();
+  const int kmax = s.max_iter - res.iters_bulk;
+  for (k = 0;; ++k) {
+    if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
+    res.residual_proxy = rho;
+    if (!std::isfinite(rho) || rho > 1e6) {
+      status = IPR_EDIVERGED;
+      break;
+    }
+    if (rho < tol) {
+      if (ns) {  // R_k = I - A C_k is the true residual
+        res.residual_true = rho;
+        status = IPR_OK;
+        break;
+      }
+      if (!s.verify) {
+        status = IPR_OK;
+        break;
+      }
+      double tau;
+      if (int rc = sv.true_residual(&tau)) return rc;
+      res.residual_true = tau;
+      verified_at = k;
+      if (tau < tol) {
+        status = IPR_OK;
+        break;
+      }
+      if (++failed_verify >= 2 && !(tau < 0.5 * last_tau)) {
+        status = IPR_EFLOOR;
+        break;
+      }
+      last_tau = tau;
+    }
+    if (rho < 1.0) {
+      if (rho < s.stall_ratio * best) {
+        best = rho;
+        stale = 0;
+      } else if (++stale >= 3) {
+        status = IPR_EFLOOR;
+        break;
+      }
+    }
+    if (k >= kmax) break;
+    if (int rc = sv.step(ns)) return rc;
+  }
+  tm.mark(4);
+  res.iters_fp64 = k;
+  if (ns && status != IPR_EDIVERGED) {
+    res.residual_true = rho;  // of the returned iterate
+  } else if (status != IPR_OK && s.verify && status != IPR_EDIVERGED && verified_at != k) {
+    double tau;
+    if (int rc = sv.true_residual(&tau)) return rc;
+    res.residual_true = tau;
+  }
+  if (sv.C() != dC) HIP_TRY(copy(sv.C(), nn, dC, stream));
+  tm.mark(5);
+  HIP_TRY(hipStreamSynchronize(stream));
+  res.ms_norms = tm.ms(0, 1);
+  res.ms_init = tm.ms(1, 2);
+  res.ms_bulk = tm.ms(2, 3);
+  res.ms_refine = tm.ms(3, 4);
+  res.ms_verify = tm.ms(4, 5);
+  res.status = status;
+  res.gemms = sv.prod.gemms;
+  sv.prod.totals(&res.gemm_launches, &res.ms_gemm, &res.gemm_flops);
+  if (out) *out = res;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""GPU parity of the FP64 path (through the C ABI) against the oracle."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import iteration as it
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+U = np.finfo(np.float64).eps / 2
+
+
+@pytest.fixture(scope="module")
+def ipr():
+    import paper_1703_02283_amd as m
+    m.load()
+    return m
+
+
+def _gemm_bound(L, R):
+    # |L^T R - fl(L^T R)| <= n u |L|^T |R| (entrywise), with slack for FMA order
+    n = L.shape[0]
+    return 2 * n * U * (np.abs(L).T @ np.abs(R)) + 1e-300
+
+
+@pytest.mark.parametrize("n", [1, 16, 64, 128, 200, 257, 384])
+def test_gemm_full_matches_numpy(ipr, n):
+    say("gemm full n", n)
+    rng = np.random.default_rng(n)
+    L = rng.standard_normal((n, n))
+    R = rng.standard_normal((n, n))
+    X = rng.standard_normal((n, n))
+    D = host(ipr.ipr_gemm(dev(L), dev(R), dev(X), alpha=0.5, beta=-2.0, gamma=3.0))
+    ref = 0.5 * (L.T @ R) - 2.0 * X + 3.0 * np.eye(n)
+    assert np.all(np.abs(D - ref) <= 0.5 * _gemm_bound(L, R) + 4 * U * (np.abs(ref) + 1))
+
+
+@pytest.mark.parametrize("n", [64, 130, 256, 385])
+def test_gemm_triangle_mirrors_upper(ipr, n):
+    say("gemm triangle n", n)
+    rng = np.random.default_rng(n + 1)
+    S = rng.standard_normal((n, n))
+    S = S + S.T
+    T = rng.standard_normal((n, n))
+    T = T @ T.T / n
+    D = host(ipr.ipr_gemm(dev(S), dev(T), None, triangle=True))
+    ref = S @ T                        # not symmetric: only its upper triangle is compared
+    up = np.triu_indices(n)
+    assert np.array_equal(D, D.T)
+    assert np.all(np.abs(D[up] - ref[up]) <= _gemm_bound(S, T)[up])
+
+
+def test_norms(ipr):
+    a = w.kernel_matrix(300, seed=2)
+    a[3, 7] = a[7, 3] = -5.0
+    n1, ni = ipr.ipr_norms(dev(a))
+    assert abs(n1 - it.norm_1(a)) <= 1e-14 * n1
+    assert abs(ni - it.norm_inf(a)) <= 1e-14 * ni
+
+
+def _solve(ipr, a, p, tol, **sched):
+    s = ipr.ipr_schedule_default(**sched)
+    C, res = ipr.ipr_solve(dev(a), p, tol, schedule=s)
+    return host(C), res
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n,tri", [(96, 1), (257, 1), (300, 0), (130, 0)])
+def test_solve_matches_oracle(ipr, p, n, tri):
+    say("solve p", p, "n", n, "tri", tri)
+    a, lam, q = w.spd_log_spectrum(n, 1e3, seed=100 + n + p)
+    c, res = _solve(ipr, a, p, 1e-10, triangle=tri)
+    ref = it.solve(a, p, 1e-10)
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert it.rel_fro(c, ref.c) <= 1e-10
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    assert abs(res.iters_fp64 - ref.iters) <= 1
+    assert res.residual_true < 1e-10
+    assert np.array_equal(c, c.T)        # exactly symmetric in both modes
+    assert abs(res.norm1 - it.norm_1(a)) <= 1e-13 * res.norm1
+
+
+def test_cfg1_spd256_p2_golden_count(ipr):
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "iteration_counts.json")))
+    g = gold["counts"]["spd_n256_logU[1e-2,1]_seed0"]
+    a, lam, q = w.spd_log_spectrum(256, lam_range=(1e-2, 1.0), seed=0)
+    c, res = _solve(ipr, a, 2, 1e-12)
+    ref = it.solve(a, 2, 1e-12)
+    assert res.status == ipr.IPR_OK
+    assert abs(res.iters_fp64 - g["p2"]["identity"]) <= 1
+    assert it.rel_fro(c, ref.c) <= 1e-10
+
+
+def test_paper_eq3_start(ipr):
+    # p = 1 from eq. (3) converges (Newton-Schulz); counts agree with the oracle
+    a, _, _ = w.spd_log_spectrum(128, 1e2, seed=7)
+    c, res = _solve(ipr, a, 1, 1e-10, init=ipr.IPR_INIT_PAPER_EQ3, max_iter=200)
+    ref = it.solve(a, 1, 1e-10, init="paper", max_iter=200)
+    assert res.status == ipr.IPR_OK and ref.status == it.OK
+    assert abs(res.iters_fp64 - ref.iters) <= 1
+    assert it.rel_fro(c, np.linalg.inv(a)) < 1e-11
+    # p = 2 from eq. (3) floors above 1e-12 at kappa ~ 1e2 (as the oracle does)
+    a, _, _ = w.spd_log_spectrum(256, lam_range=(1e-2, 1.0), seed=0)
+    c, res = _solve(ipr, a, 2, 1e-12, init=ipr.IPR_INIT_PAPER_EQ3, max_iter=200)
+    ref = it.solve(a, 2, 1e-12, init="paper", max_iter=200)
+    assert ref.status == it.EFLOOR and res.status in (ipr.IPR_EFLOOR, ipr.IPR_EMAXITER)
+    assert it.rel_fro(c, it.eig_root(a, 2)) < 1e-8
+
+
+def test_guard_falls_back_for_eq3_small_spectrum(ipr):
+    a = 0.1 * np.eye(40)
+    c, res = _solve(ipr, a, 2, 1e-12, init=ipr.IPR_INIT_PAPER_EQ3)
+    assert res.fallback_used == 1 and res.status == ipr.IPR_OK
+    assert np.max(np.abs(c - 0.1 ** -0.5 * np.eye(40))) < 1e-12
+    with pytest.raises(ipr.IprError):
+        _solve(ipr, a, 2, 1e-12, init=ipr.IPR_INIT_PAPER_EQ3, guard_fallback=0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_poly_start(ipr, p):
+    a, _, _ = w.spd_log_spectrum(200, 1e3, seed=21)
+    b = (1.2, -0.3, 0.05)
+    c, res = _solve(ipr, a, p, 1e-10, init=ipr.IPR_INIT_POLY, poly=b)
+    ref = it.solve(a, p, 1e-10, init="poly", poly=b)
+    assert res.status == ipr.IPR_OK and res.fallback_used == 0
+    assert abs(res.iters_fp64 - ref.iters) <= 1
+    assert it.rel_fro(c, ref.c) <= 1e-10
+
+
+def test_degenerate_inputs(ipr):
+    c, res = _solve(ipr, np.array([[4.0]]), 2, 1e-14)
+    assert res.status == ipr.IPR_OK and abs(c[0, 0] - 0.5) < 1e-15
+    lam = np.array([0.9, 0.013, 0.27, 1.0, 0.5, 0.0031])
+    c, res = _solve(ipr, np.diag(lam), 3, 1e-13)
+    assert res.status == ipr.IPR_OK
+    assert np.max(np.abs(np.diag(c) - lam ** (-1 / 3)) / lam ** (-1 / 3)) < 1e-13
+    assert np.count_nonzero(c - np.diag(np.diag(c))) == 0
+    c, res = _solve(ipr, 0.37 * np.eye(33), 4, 1e-14)
+    assert res.status == ipr.IPR_OK and np.max(np.abs(c - 0.37 ** -0.25 * np.eye(33))) < 1e-14
+
+
+def test_argument_errors(ipr):
+    import torch
+    a = dev(np.eye(8))
+    with pytest.raises(ipr.IprError):
+        ipr.ipr_solve(a, 2, 0.0)
+    with pytest.raises(ipr.IprError):
+        ipr.ipr_solve(a, 0, 1e-10)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ipr.IprError):
+        ipr.ipr_solve(a, 2, 1e-10, workspace=small)
+
+
+def test_maxiter_and_divergence_status(ipr):
+    a, _, _ = w.spd_log_spectrum(64, 1e4, seed=3)
+    c, res = _solve(ipr, a, 2, 1e-10, max_iter=3)
+    assert res.status == ipr.IPR_EMAXITER and res.iters_fp64 == 3
+    ind = np.diag(np.linspace(-1.0, 1.0, 32))      # indefinite: diverges
+    c, res = _solve(ipr, ind, 2, 1e-10)
+    assert res.status in (ipr.IPR_EDIVERGED, ipr.IPR_EFLOOR, ipr.IPR_EMAXITER)
+    assert res.status != ipr.IPR_OK
+
+
+def test_repeat_runs_are_bitwise_identical(ipr):
+    a, _, _ = w.spd_log_spectrum(320, 1e3, seed=5)
+    c1, r1 = _solve(ipr, a, 2, 1e-10)
+    c2, r2 = _solve(ipr, a, 2, 1e-10)
+    assert np.array_equal(c1, c2) and r1.residual_proxy == r2.residual_proxy

@@ -1,0 +1,71 @@
+"""Parity at the full sizes the bench runs: n = 16384 (p = 2, Householder
+spectrum matrices) and the n = 4096 kernel matrix (p = 1, 2, 3), in the
+bench's launch configuration (default schedule: FP64, identity start,
+triangle products)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import iteration as it
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = json.load(open(os.path.join(ROOT, "tests", "golden", "iteration_counts.json")))["counts"]
+
+
+@pytest.fixture(scope="module")
+def ipr():
+    import paper_1703_02283_amd as m
+    m.load()
+    return m
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e2])
+def test_householder_16384_p2(ipr, kappa):
+    import torch
+    n, p = 16384, 2
+    say("full size householder n", n, "kappa", kappa)
+    a, lam = w.householder_spd(n, kappa, seed=0)
+    A = dev(a)
+    del a
+    C, res = ipr.ipr_solve(A, p, 1e-10)
+    say("  status", res.status, "iters", res.iters_fp64, "residual", res.residual_true)
+    c = host(C)
+    del A, C
+    torch.cuda.empty_cache()
+    ref = it.householder_root(n, kappa, 0, p)
+    err = it.rel_fro(c, ref)
+    say("  rel err vs definition", err)
+    g = GOLD[f"householder_n16384_kappa{kappa:g}_seed0"]["p2"]["identity"]
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert res.residual_true < 1e-10
+    assert err <= 1e-10
+    assert abs(res.iters_fp64 - g) <= 1
+    assert np.array_equal(c[:64, :], c[:, :64].T)
+
+
+@pytest.fixture(scope="module")
+def kernel4096():
+    a = w.kernel_matrix(4096, seed=0)
+    lam, v = np.linalg.eigh(a)
+    return a, lam, v
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_kernel_matrix_4096(ipr, kernel4096, p):
+    a, lam, v = kernel4096
+    say("kernel matrix n 4096 p", p)
+    C, res = ipr.ipr_solve(dev(a), p, 1e-10)
+    c = host(C)
+    ref = (v * lam ** (-1.0 / p)) @ v.T
+    err = it.rel_fro(c, ref)
+    say("  status", res.status, "iters", res.iters_fp64, "residual", res.residual_true, "err", err)
+    g = GOLD["kernel_n4096_seed0"][f"p{p}"]["identity"]
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert err <= 1e-10
+    assert abs(res.iters_fp64 - g) <= 1

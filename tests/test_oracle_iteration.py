@@ -177,3 +177,16 @@ def test_newton_schulz_self_corrects_perturbation():
     start = inv + 0.5 * (e + e.T)
     res = it.solve(a, 1, 1e-11, init=start, evaluation="newton_schulz")
     assert res.status == it.OK and it.rel_fro(res.c, inv) < 1e-11
+
+
+def test_householder_root_is_the_definition():
+    # the O(n^2 k) construction equals eigh's root and inverts A^p
+    a, lam = w.householder_spd(300, 1e3, seed=4, nrefl=16)
+    assert np.allclose(np.sort(np.linalg.eigvalsh(a)), np.sort(lam), atol=1e-14)
+    lam2, v, t = w.householder_factors(300, 1e3, 4, nrefl=16)
+    for p in (1, 2, 3):
+        x = w.householder_congruence(v, t, lam2 ** (-1.0 / p))
+        assert it.rel_fro(x, it.eig_root(a, p)) < 1e-12
+        assert np.linalg.norm(np.eye(300) - np.linalg.matrix_power(x, p) @ a) < 1e-10
+    a64, _ = w.householder_spd(256, 1e2, seed=9)
+    assert it.rel_fro(it.householder_root(256, 1e2, 9, 2), it.eig_root(a64, 2)) < 1e-12

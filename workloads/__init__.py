@@ -97,36 +97,45 @@ def kernel_matrix(n: int = 4096, seed: int = 0, box: float = 20.0,
     return 0.5 * (a + a.T)
 
 
-def householder_spd(n: int, kappa: float, seed: int = 0, nrefl: int = 64):
-    """A = H diag(lam) H^T with H = H_1 H_2 ... H_k, H_i = I - 2 v_i v_i^T / |v_i|^2.
+def householder_factors(n: int, kappa: float, seed: int = 0, nrefl: int = 64):
+    """Spectrum and compact-WY form of H = H_1 H_2 ... H_k, H_i = I - 2 v_i v_i^T / |v_i|^2.
 
     Draw order: lam (n uniforms, endpoints pinned to 1/kappa and 1), then the k
-    Gaussian vectors v_i (k*n normals). H is applied in compact-WY form
-    H = I - V T V^T, so building A costs O(n^2 k) instead of O(n^3).
-    Returns (A, lam).
-    """
+    Gaussian vectors v_i (k*n normals). Returns (lam, V, T) with H = I - V T V^T,
+    V n x k with unit columns and T k x k upper triangular."""
     rng = np.random.default_rng(seed)
     lam = log_spectrum(n, kappa, rng, pin_ends=True)
     v = rng.standard_normal((nrefl, n))
     v /= np.linalg.norm(v, axis=1, keepdims=True)
-    vmat = v.T                                     # n x k, unit columns
-    # compact WY: H_1...H_k = I - V T V^T with T upper triangular (k x k)
+    vmat = v.T
     t = np.zeros((nrefl, nrefl))
     for j in range(nrefl):
         t[j, j] = 2.0
         if j:
             t[:j, j] = -2.0 * t[:j, :j] @ (vmat[:, :j].T @ vmat[:, j])
-    # A = (I - W) L (I - W)^T, W = V T V^T, L = diag(lam)
-    vl = vmat.T * lam                               # k x n  = V^T L
-    wl = vmat @ (t @ vl)                            # n x n  = W L
-    k_small = vl @ vmat                             # k x k  = V^T L V
-    wlw = vmat @ (t @ k_small @ t.T) @ vmat.T       # n x n  = W L W^T
-    a = wlw
-    a -= wl
-    a -= wl.T
-    a[np.diag_indices(n)] += lam
-    a = 0.5 * (a + a.T)
-    return a, lam
+    return lam, vmat, t
+
+
+def householder_congruence(vmat: np.ndarray, t: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """H diag(d) H^T for H = I - V T V^T in O(n^2 k): with W = V T V^T,
+    (I - W) D (I - W)^T = D - W D - D W^T + W D W^T. Exactly symmetric."""
+    n = vmat.shape[0]
+    vd = vmat.T * d                                 # k x n  = V^T D
+    wd = vmat @ (t @ vd)                            # n x n  = W D
+    k_small = vd @ vmat                             # k x k  = V^T D V
+    a = vmat @ (t @ k_small @ t.T) @ vmat.T         # n x n  = W D W^T
+    a -= wd
+    a -= wd.T
+    a[np.diag_indices(n)] += d
+    return 0.5 * (a + a.T)
+
+
+def householder_spd(n: int, kappa: float, seed: int = 0, nrefl: int = 64):
+    """A = H diag(lam) H^T with H a product of ``nrefl`` Householder reflectors
+    (see ``householder_factors`` for the draw order). Building A costs O(n^2 k)
+    instead of O(n^3). Returns (A, lam)."""
+    lam, vmat, t = householder_factors(n, kappa, seed, nrefl)
+    return householder_congruence(vmat, t, lam), lam
 
 
 def batch_recipe(count: int = 2000, base_seed: int = 1000,
