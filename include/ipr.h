@@ -76,6 +76,7 @@ typedef struct {
   double poly[3];      /* b0, b1, b2 for IPR_INIT_POLY */
   const float* mlp_params; /* device, IPR_MLP_NPARAM floats, for IPR_INIT_LEARNED */
   int timing;          /* 1: time every matrix product with device events (ms_gemm, gemm_flops) */
+  int tile;            /* ipr_solve_batched: product tile edge 32 or 64; 0 = size-bucket table */
 } ipr_schedule;
 
 typedef struct {
@@ -134,6 +135,22 @@ int ipr_solve_batched(const double* dA_packed, double* dC_packed, const int64_t*
                       const int* n, const int* p, int batch, double tol,
                       const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
                       hipStream_t stream);
+
+/* Size buckets of the batched solver's tile table: bucket b holds the orders
+ * n <= IPR_BATCH_BUCKET_MAX(b) (48, 96, 192, 384, 768, 1024). */
+#define IPR_BATCH_BUCKETS 6
+
+/* Times every tile edge (32, 64) on synthetic batches of each bucket's
+ * largest order (a fixed 3 iterations per matrix, one persistent launch each)
+ * and stores the fastest in the process-wide table used when schedule.tile is
+ * 0; the table is copied to host tiles_out[IPR_BATCH_BUCKETS] (may be NULL).
+ * Each bucket times up to 512 matrices, as many as fit in dWork (9 n^2
+ * doubles each); a bucket none fits in keeps its entry. */
+int ipr_tune_batched(void* dWork, size_t work_bytes, int* tiles_out, hipStream_t stream);
+
+/* Reads or replaces the process-wide tile table (host arrays of IPR_BATCH_BUCKETS). */
+int ipr_get_batched_tiles(int* tiles);
+int ipr_set_batched_tiles(const int* tiles);
 
 /* D = L^T R for n x n float64 matrices on the FP64 matrix cores (the product
  * every step of eq. (1) is made of), followed by D <- alpha D + beta X + gamma I.

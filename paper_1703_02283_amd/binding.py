@@ -23,7 +23,8 @@ class IprSchedule(ct.Structure):
     _fields_ = [("init", ct.c_int), ("bulk_dtype", ct.c_int), ("max_iter", ct.c_int),
                 ("triangle", ct.c_int), ("guard_fallback", ct.c_int), ("verify", ct.c_int),
                 ("bulk_switch", ct.c_double), ("stall_ratio", ct.c_double),
-                ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int)]
+                ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int),
+                ("tile", ct.c_int)]
 
 
 class IprResult(ct.Structure):
@@ -81,6 +82,9 @@ _SIGS = {
                                       ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ipr_mlp_workspace": (ct.c_size_t, [ct.c_int]),
     "ipr_last_error": (ct.c_char_p, []),
+    "ipr_tune_batched": (ct.c_int, [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
+    "ipr_get_batched_tiles": (ct.c_int, [ct.c_void_p]),
+    "ipr_set_batched_tiles": (ct.c_int, [ct.c_void_p]),
 }
 
 
@@ -205,6 +209,29 @@ def ipr_solve_batched(A_packed, offsets, ns, ps, tol, schedule=None, out=None,
                                   ct.byref(sch), res, _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, allow=(IPR_EMAXITER, IPR_EFLOOR, IPR_EDIVERGED))
     return C, list(res)
+
+
+IPR_BATCH_BUCKETS = 6
+
+
+def ipr_tune_batched(workspace_bytes=None, device="cuda", stream=None):
+    """Runs the batched solver's tile autotuner; returns the table."""
+    need = ipr_workspace_size(1024, 1, 1)
+    ws = _workspace(max(need, workspace_bytes or 0), device)
+    out = (ct.c_int * IPR_BATCH_BUCKETS)()
+    _check(_fn("ipr_tune_batched")(_ptr(ws), ws.numel(), out, _stream(stream)))
+    return list(out)
+
+
+def ipr_get_batched_tiles():
+    out = (ct.c_int * IPR_BATCH_BUCKETS)()
+    _check(_fn("ipr_get_batched_tiles")(out))
+    return list(out)
+
+
+def ipr_set_batched_tiles(tiles):
+    arr = (ct.c_int * IPR_BATCH_BUCKETS)(*[int(t) for t in tiles])
+    _check(_fn("ipr_set_batched_tiles")(arr))
 
 
 def ipr_gemm(L, R, X=None, alpha=1.0, beta=0.0, gamma=0.0, triangle=False, out=None,

@@ -1,0 +1,38 @@
+// Persistent batched solver (batched.hip): per-matrix work items and results.
+#pragma once
+#include <cstdint>
+
+#include "ipr_internal.h"
+
+namespace ipr {
+
+struct BatchItem {
+  int64_t a_off;   // element offset of A_i (and C_i) in the packed buffers
+  int64_t s_off;   // element offset of its 7 n_i^2 scratch matrices
+  int n, p, tile, pad;
+};
+
+struct BatchResult {
+  int status, iters_bulk, iters_fp64, pad;
+  double residual_proxy, residual_true, norm1, norminf;
+};
+
+struct BatchArgs {
+  const double* A;
+  double* C;
+  double* scratch;
+  const BatchItem* items;
+  const int* order;      // items in workgroup order
+  const int* wg_begin;   // workgroup w owns order[wg_begin[w] .. wg_begin[w+1])
+  BatchResult* results;  // by item index
+  double tol, bulk_switch, stall_ratio;
+  int max_iter, bulk_bf16;
+};
+
+hipError_t batched_launch(const BatchArgs& args, int grid, hipStream_t stream);
+
+// Fills matrices with a deterministic SPD pattern (autotuner input):
+// A_i = diag(1 + j/n) + small symmetric off-diagonal band.
+hipError_t batched_fill_test(double* A, const BatchItem* items, int count, hipStream_t stream);
+
+}  // namespace ipr

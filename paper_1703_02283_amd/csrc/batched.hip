@@ -1,0 +1,555 @@
+// Many independent solves in one persistent launch.
+//
+// Every matrix of the batch is owned by one workgroup, which runs the whole
+// method of Section II on it: the norms of eq. (3), the scaled-identity start,
+// the coupled form of eq. (1) (C' = C N, M' = N^p M, N = I + (I - M)/p) and
+// the final check of ||I - C^p A||_F, with the iteration loop, the stopping
+// rules and the Frobenius reductions on the device. A workgroup therefore
+// never waits for another, and the launch needs no grid-wide barrier. The
+// host assigns matrices to workgroups by longest-processing-time (estimated
+// work n^3 (p + 1)); each workgroup walks its list in order and the grid has
+// drained when every list is done.
+//
+// Products inside a workgroup sweep the output tiles of D = L^T R one by one
+// (triangle only: every product is a polynomial in A), FP64 MFMA
+// 16x16x4 with the same operand staging as the large-matrix kernel. The tile
+// edge (32 or 64) is chosen per matrix from a size-bucket table that the
+// autotuner fills. For p = 1 a bf16 bulk phase (Newton-Schulz order, operands
+// rounded to bf16 while they are staged into LDS, fp32 accumulation) can run
+// before the FP64 refinement.
+#include <cstdint>
+
+#include "batched.h"
+#include "kernels_common.h"
+
+namespace ipr {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 256;
+constexpr int BK = 16;
+
+struct Smem {
+  double L[2][BK][64 + 16];
+  double R[2][BK][64 + 16];
+  double red[NT / 64];
+  double bcast[4];
+};
+
+__device__ __forceinline__ double block_sum(double v, Smem& sm) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm.red[wave] = v;
+  __syncthreads();
+  const double s = (sm.red[0] + sm.red[1]) + (sm.red[2] + sm.red[3]);
+  __syncthreads();
+  return s;  // every thread
+}
+
+__device__ __forceinline__ double block_max(double v, Smem& sm) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm.red[wave] = v;
+  __syncthreads();
+  const double s = fmax(fmax(sm.red[0], sm.red[1]), fmax(sm.red[2], sm.red[3]));
+  __syncthreads();
+  return s;
+}
+
+// Epilogue of an in-workgroup product, applied to element (i, j) (i <= j in
+// triangle mode, mirrored): out = alpha acc + beta X + gamma delta;
+// D = out; Nout = ((p+1) delta - out)/p when Nout; returns the element's
+// contribution to sum (out - pd delta)^2 (counting mirrored ones twice).
+struct WEpi {
+  double alpha = 1.0, beta = 0.0, gamma = 0.0, pd = 0.0;
+  const double* X = nullptr;
+  double* D = nullptr;
+  double* Nout = nullptr;
+  double np1 = 0.0, inv_p = 0.0;
+};
+
+__device__ __forceinline__ double wepi(const WEpi& e, int n, int tri, int i, int j, double acc) {
+  if (i >= n || j >= n || (tri && i > j)) return 0.0;
+  const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+  const bool mirror = tri && i != j;
+  double v = e.alpha * acc;
+  if (e.X) v += e.beta * e.X[ij];
+  if (i == j) v += e.gamma;
+  if (e.D) {
+    e.D[ij] = v;
+    if (mirror) e.D[ji] = v;
+  }
+  if (e.Nout) {
+    const double nv = ((i == j ? e.np1 : 0.0) - v) * e.inv_p;
+    e.Nout[ij] = nv;
+    if (mirror) e.Nout[ji] = nv;
+  }
+  const double q = i == j ? v - e.pd : v;
+  return mirror ? 2.0 * q * q : q * q;
+}
+
+// One output tile of edge TB = 2 WT (4 waves, 2 x 2, each WT x WT) of
+// D = L^T R, FP64 or bf16-rounded operands (LP).
+template <int WT, bool LP>
+__device__ double wg_tile(const double* __restrict__ L, const double* __restrict__ R, int n,
+                          int i0, int j0, int tri, const WEpi& e, Smem& sm) {
+  constexpr int TB = 2 * WT;
+  constexpr int FB = WT / 16;  // 16 x 16 blocks per wave edge
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WT, wn0 = (wave & 1) * WT;
+  const int fr = lane >> 4, fc = lane & 15;
+  v4d acc[FB][FB];
+  v4f accf[FB][FB];
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b) {
+      acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+      accf[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+  // staging: BK x TB doubles per operand, NT threads, CH elements each
+  constexpr int CH = BK * TB / NT;  // 8 (TB=128), 4 (64), 2 (32)
+  double la[CH], ra[CH];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int idx = tid + q * NT;
+      const int kr = idx / TB, c = idx % TB;
+      const int k = k0 + kr;
+      la[q] = (k < n && i0 + c < n) ? L[(size_t)k * n + i0 + c] : 0.0;
+      ra[q] = (k < n && j0 + c < n) ? R[(size_t)k * n + j0 + c] : 0.0;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int idx = tid + q * NT;
+      const int kr = idx / TB, c = idx % TB;
+      sm.L[buf][kr][c] = la[q];
+      sm.R[buf][kr][c] = ra[q];
+    }
+  };
+  const int nk = (n + BK - 1) / BK;
+  gload(0);
+  __syncthreads();  // previous users of the staging buffers are done
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    if constexpr (!LP) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double av[FB], bv[FB];
+#pragma unroll
+        for (int a = 0; a < FB; ++a) av[a] = sm.L[buf][kk + fr][wm0 + a * 16 + fc];
+#pragma unroll
+        for (int b = 0; b < FB; ++b) bv[b] = sm.R[buf][kk + fr][wn0 + b * 16 + fc];
+#pragma unroll
+        for (int a = 0; a < FB; ++a)
+#pragma unroll
+          for (int b = 0; b < FB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    } else {
+      // The bf16 16x16x32 operand spans 32 k and a slab holds 16: lanes whose
+      // k is 16..31 supply zeros (half of the instruction's k width idles).
+      v8bf av[FB], bv[FB];
+#pragma unroll
+      for (int a = 0; a < FB; ++a) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = fr * 8 + t;  // 0..31; k >= 16 are zero
+          av[a][t] = k < BK ? (__bf16)(float)sm.L[buf][k][wm0 + a * 16 + fc] : (__bf16)0.0f;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < FB; ++b) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = fr * 8 + t;
+          bv[b][t] = k < BK ? (__bf16)(float)sm.R[buf][k][wn0 + b * 16 + fc] : (__bf16)0.0f;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < FB; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+          accf[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], accf[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  double ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (!LP)
+          ps += wepi(e, n, tri, i0 + wm0 + a * 16 + fr + 4 * r, j0 + wn0 + b * 16 + fc,
+                     acc[a][b][r]);
+        else
+          ps += wepi(e, n, tri, i0 + wm0 + a * 16 + 4 * fr + r, j0 + wn0 + b * 16 + fc,
+                     (double)accf[a][b][r]);
+      }
+  return ps;
+}
+
+// Whole product D = L^T R inside the workgroup; returns the block-summed
+// partial (every thread). tile: 32 or 64 (a 128 edge would need more
+// registers than a persistent kernel can hold beside its control state).
+template <bool LP>
+__device__ double wg_product(const double* L, const double* R, int n, int tri, int tile,
+                             const WEpi& e, Smem& sm) {
+  const int nt = (n + tile - 1) / tile;
+  double ps = 0.0;
+  for (int bi = 0; bi < nt; ++bi)
+    for (int bj = tri ? bi : 0; bj < nt; ++bj) {
+      if (tile == 64)
+        ps += wg_tile<32, LP>(L, R, n, bi * 64, bj * 64, tri, e, sm);
+      else
+        ps += wg_tile<16, LP>(L, R, n, bi * 32, bj * 32, tri, e, sm);
+    }
+  __syncthreads();  // the product is complete and visible to the workgroup
+  return block_sum(ps, sm);
+}
+
+// A queue of products run by one (non-inlined) routine: keeping a single
+// copy of the tile loops keeps the kernel's register allocation small.
+struct ProdDesc {
+  const double* L;
+  const double* R;
+  int tri, lowp;
+  WEpi e;
+};
+constexpr int QMAX = 12;
+
+// Workgroup-uniform values read from memory land in vector registers; moving
+// them to scalar registers keeps the tile loops' vector registers free.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* v) { return (T*)uni((uint64_t)v); }
+__device__ __forceinline__ double uni(double v) {
+  return __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, v)));
+}
+
+// Runs q[0..count) in order; returns the block-summed partial of the last.
+__device__ double run_products(const ProdDesc* q, int count, int n, int tile,
+                                            Smem* sm) {
+  double ps = 0.0;
+  for (int i = 0; i < count; ++i) {
+    ProdDesc d = q[i];
+    d.L = uni(d.L);
+    d.R = uni(d.R);
+    d.tri = uni(d.tri);
+    d.lowp = uni(d.lowp);
+    d.e.alpha = uni(d.e.alpha);
+    d.e.beta = uni(d.e.beta);
+    d.e.gamma = uni(d.e.gamma);
+    d.e.pd = uni(d.e.pd);
+    d.e.X = uni(d.e.X);
+    d.e.D = uni(d.e.D);
+    d.e.Nout = uni(d.e.Nout);
+    d.e.np1 = uni(d.e.np1);
+    d.e.inv_p = uni(d.e.inv_p);
+    ps = d.lowp ? wg_product<true>(d.L, d.R, n, d.tri, tile, d.e, *sm)
+                : wg_product<false>(d.L, d.R, n, d.tri, tile, d.e, *sm);
+  }
+  return ps;
+}
+
+struct Bufs {
+  const double* A;
+  double* C[2];
+  double* M[2];
+  double* N[2];
+  double* X[2];
+};
+
+__global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
+  __shared__ Smem sm;
+  __shared__ __attribute__((aligned(16))) char qraw[QMAX * sizeof(ProdDesc)];
+  ProdDesc* q = reinterpret_cast<ProdDesc*>(qraw);
+  const int tid = threadIdx.x;
+  const int w = blockIdx.x;
+  // each item's n (1..1024), p (1..8) and tile were checked on the host
+  for (int li = args.wg_begin[w]; li < args.wg_begin[w + 1]; ++li) {
+    const BatchItem it = args.items[uni(args.order[li])];
+    const int n = uni(it.n), p = uni(it.p), tile = uni(it.tile);
+    const size_t nn = (size_t)n * n;
+    Bufs b;
+    b.A = uni(args.A + it.a_off);
+    double* dC = uni(args.C + it.a_off);  // C_i sits where A_i sits in its buffer
+    double* s = uni(args.scratch + it.s_off);
+    b.C[0] = dC;
+    b.C[1] = s;
+    b.M[0] = s + nn;
+    b.M[1] = s + 2 * nn;
+    b.N[0] = s + 3 * nn;
+    b.N[1] = s + 4 * nn;
+    b.X[0] = s + 5 * nn;
+    b.X[1] = s + 6 * nn;
+    BatchResult res;
+    res.status = 2;  // EMAXITER unless set below
+    res.iters_bulk = res.iters_fp64 = 0;
+    res.pad = 0;
+    res.residual_true = -1.0;
+    res.residual_proxy = 0.0;
+
+    // ---- norms of eq. (3)
+    double cmax = 0.0, rmax = 0.0;
+    for (int j = tid; j < n; j += NT) {  // column sums (coalesced over j)
+      double cs = 0.0;
+      for (int i = 0; i < n; ++i) cs += fabs(b.A[(size_t)i * n + j]);
+      cmax = fmax(cmax, cs);
+    }
+    for (int i = tid >> 6; i < n; i += NT / 64) {  // row sums: one wave per row
+      double rs = 0.0;
+      for (int j = tid & 63; j < n; j += 64) rs += fabs(b.A[(size_t)i * n + j]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+      rmax = fmax(rmax, rs);
+    }
+    const double n1 = block_max(cmax, sm), ninf = block_max(rmax, sm);
+    const double s2 = n1 * ninf, sigma = sqrt(s2);
+    res.norm1 = n1;
+    res.norminf = ninf;
+    const double c = pow(s2, -1.0 / (2.0 * p)), cp = 1.0 / sigma, inv_p = 1.0 / p;
+
+    // scaled-identity start: C = c I, M = c^p A, N = ((p+1) I - M)/p
+    auto start = [&]() {
+      double ps = 0.0;
+      for (size_t t = tid; t < nn; t += NT) {
+        const size_t i = t / n, j = t - i * n;
+        const double d = i == j ? 1.0 : 0.0;
+        const double m = cp * b.A[t];
+        b.C[0][t] = c * d;
+        b.M[0][t] = m;
+        b.N[0][t] = d + (d - m) * inv_p;
+        ps += (d - m) * (d - m);
+      }
+      __syncthreads();
+      return sqrt(block_sum(ps, sm));
+    };
+    double rho = start();
+    int ci = 0, mi = 0, ni = 0;
+
+    // Newton-Schulz products (p = 1): R = I - A C into b.X[0]; C' = C + C R.
+    double* Rn = b.X[0];
+    auto ns = [&](bool with_update, bool lowp) {
+      __syncthreads();
+      if (tid == 0) {
+        int k = 0;
+        if (with_update) {
+          ProdDesc d;
+          d.L = b.C[ci];
+          d.R = Rn;
+          d.tri = 1;
+          d.lowp = lowp;
+          d.e = WEpi();
+          d.e.beta = 1.0;
+          d.e.X = b.C[ci];
+          d.e.D = b.C[ci ^ 1];
+          q[k++] = d;
+        }
+        ProdDesc r;
+        r.L = b.A;
+        r.R = with_update ? b.C[ci ^ 1] : b.C[ci];
+        r.tri = 0;  // full: the Newton-Schulz residual must not be symmetrised
+        r.lowp = lowp;
+        r.e = WEpi();
+        r.e.alpha = -1.0;
+        r.e.gamma = 1.0;
+        r.e.D = Rn;
+        q[k++] = r;
+      }
+      __syncthreads();
+      const double r2 = run_products(q, with_update ? 2 : 1, n, tile, &sm);
+      if (with_update) ci ^= 1;
+      return sqrt(r2);
+    };
+
+    const bool lp = args.bulk_bf16 && p == 1;
+    int kb = 0;
+    bool use_ns = false;
+    if (lp) {
+      rho = ns(false, true);
+      double best = 1e300;
+      int stale = 0;
+      for (kb = 0; kb < args.max_iter; ++kb) {
+        if (!(rho <= 1e6)) break;
+        if (rho < args.bulk_switch) break;
+        if (rho < 1.0) {
+          if (rho < args.stall_ratio * best) {
+            best = rho;
+            stale = 0;
+          } else if (++stale >= 2) {
+            break;
+          }
+        }
+        rho = ns(true, true);
+      }
+      res.iters_bulk = kb;
+      if (rho <= 1e6) {
+        rho = ns(false, false);  // FP64 residual of the bulk result
+        use_ns = true;
+      } else {                   // bulk diverged: FP64 from the identity again
+        ci = 0;
+        rho = start();
+      }
+    }
+
+    // ---- FP64 iterations
+    double best = 1e300, last_tau = 1e300;
+    int stale = 0, failed = 0, k = 0;
+    const int kmax = args.max_iter - res.iters_bulk;
+    for (k = 0;; ++k) {
+      res.residual_proxy = rho;
+      if (!(rho <= 1e6)) {
+        res.status = 4;
+        break;
+      }
+      if (rho < args.tol) {
+        if (use_ns) {
+          res.residual_true = rho;
+          res.status = 0;
+          break;
+        }
+        // ||I - C^p A||_F from p full products
+        __syncthreads();
+        if (tid == 0) {
+          const double* src = b.A;
+          for (int j = 1; j <= p; ++j) {
+            ProdDesc d;
+            d.L = b.C[ci];
+            d.R = src;
+            d.tri = 0;
+            d.lowp = 0;
+            d.e = WEpi();
+            if (j == p) {
+              d.e.alpha = -1.0;
+              d.e.gamma = 1.0;
+            } else {
+              d.e.D = b.X[(j - 1) & 1];
+              src = d.e.D;
+            }
+            q[j - 1] = d;
+          }
+        }
+        __syncthreads();
+        const double tau = sqrt(run_products(q, p, n, tile, &sm));
+        res.residual_true = tau;
+        if (tau < args.tol) {
+          res.status = 0;
+          break;
+        }
+        if (++failed >= 2 && !(tau < 0.5 * last_tau)) {
+          res.status = 3;
+          break;
+        }
+        last_tau = tau;
+      }
+      if (rho < 1.0) {
+        if (rho < args.stall_ratio * best) {
+          best = rho;
+          stale = 0;
+        } else if (++stale >= 3) {
+          res.status = 3;
+          break;
+        }
+      }
+      if (k >= kmax) break;
+      if (use_ns) {
+        rho = ns(true, false);
+        continue;
+      }
+      // C' = C N; M' = N (N (... (N M))) with N' = ((p+1) I - M') / p
+      __syncthreads();
+      if (tid == 0) {
+        ProdDesc d;
+        d.L = b.C[ci];
+        d.R = b.N[ni];
+        d.tri = 1;
+        d.lowp = 0;
+        d.e = WEpi();
+        d.e.D = b.C[ci ^ 1];
+        q[0] = d;
+        const double* src = b.M[mi];
+        for (int j = 1; j <= p; ++j) {
+          ProdDesc m;
+          m.L = b.N[ni];
+          m.R = src;
+          m.tri = 1;
+          m.lowp = 0;
+          m.e = WEpi();
+          if (j == p) {
+            m.e.D = b.M[mi ^ 1];
+            m.e.Nout = b.N[ni ^ 1];
+            m.e.np1 = p + 1.0;
+            m.e.inv_p = inv_p;
+            m.e.pd = 1.0;
+          } else {
+            m.e.D = b.X[(j - 1) & 1];
+            src = m.e.D;
+          }
+          q[j] = m;
+        }
+      }
+      __syncthreads();
+      rho = sqrt(run_products(q, p + 1, n, tile, &sm));
+      ci ^= 1;
+      mi ^= 1;
+      ni ^= 1;
+    }
+    res.iters_fp64 = k;
+    if (use_ns) res.residual_true = rho;
+    if (ci != 0) {  // result into the caller's buffer
+      for (size_t t = tid; t < nn; t += NT) dC[t] = b.C[1][t];
+    }
+    __syncthreads();
+    if (tid == 0) args.results[args.order[li]] = res;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT) void fill_test_kernel(double* A, const BatchItem* items) {
+  const BatchItem it = items[blockIdx.x];
+  const int n = it.n;
+  double* a = A + it.a_off;
+  for (size_t t = threadIdx.x; t < (size_t)n * n; t += NT) {
+    const int i = (int)(t / n), j = (int)(t % n);
+    const int d = i > j ? i - j : j - i;
+    a[t] = (i == j) ? 1.0 + (double)i / n : (d <= 3 ? 0.05 / d : 0.0);
+  }
+}
+
+}  // namespace
+
+hipError_t batched_fill_test(double* A, const BatchItem* items, int count, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_test_kernel, dim3(count), dim3(NT), 0, stream, A, items);
+  return hipGetLastError();
+}
+
+hipError_t batched_launch(const BatchArgs& args, int grid, hipStream_t stream) {
+  if (!args.A || !args.C || !args.scratch || !args.items || !args.order || !args.wg_begin ||
+      !args.results)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(NT), 0, stream, args);
+  return hipGetLastError();
+}
+
+}  // namespace ipr

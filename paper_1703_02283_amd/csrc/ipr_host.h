@@ -24,6 +24,9 @@ int read_scalars(const double* d, int count, double* host, hipStream_t stream);
 // *q_pos = 1 when q > 0 on all of (0, 1].
 void poly_guard(const double b[3], int p, double* sup_phi, int* q_pos);
 
+// Workspace of ipr_solve_batched for `batch` matrices with sum n_i^2 <= n_max^2.
+size_t batched_workspace_bytes(int n_max, int batch);
+
 // Carves 256-byte aligned pieces out of a workspace.
 struct Carver {
   char* base;

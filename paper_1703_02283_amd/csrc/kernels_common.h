@@ -81,7 +81,8 @@ __device__ __forceinline__ void epilogue_element(const Epilogue& e, int n, int t
   psum += mirror ? 2.0 * q * q : q * q;
 }
 
-// Sum over the workgroup of 4 wave64s into e.partial[slot] (fixed order).
+// Sum over the workgroup's wave64s into partial[slot] (fixed order); red
+// holds one double per wave.
 __device__ __forceinline__ void store_partial(double* partial, int slot, double psum,
                                               double* red) {
 #pragma unroll
@@ -89,7 +90,12 @@ __device__ __forceinline__ void store_partial(double* partial, int slot, double 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = psum;
   __syncthreads();
-  if (threadIdx.x == 0) partial[slot] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w];
+    partial[slot] = s;
+  }
 }
 
 }  // namespace ipr

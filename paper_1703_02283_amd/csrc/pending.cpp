@@ -9,10 +9,6 @@ using namespace ipr;
 
 extern "C" {
 
-int ipr_solve_batched(const double*, double*, const int64_t*, const int*, const int*, int, double,
-                      const ipr_schedule*, ipr_result*, void*, size_t, hipStream_t) {
-  return fail(IPR_EARG, "ipr_solve_batched is not available in this build");
-}
 int ipr_features(const double*, const int64_t*, const int*, const int*, int, float*, void*, size_t,
                  hipStream_t) {
   return fail(IPR_EARG, "ipr_features is not available in this build");

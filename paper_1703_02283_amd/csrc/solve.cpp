@@ -413,7 +413,8 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
   Work w;
   bool ok;
   const int dt = s ? s->bulk_dtype : IPR_FP64;
-  return carve(n_max, p_max, dt, &w, nullptr, (size_t)-1, &ok) + 256;
+  const size_t single = carve(n_max, p_max, dt, &w, nullptr, (size_t)-1, &ok) + 256;
+  return std::max(single, batched_workspace_bytes(n_max, batch));
 }
 
 int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
