@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -189,6 +191,18 @@ def main():
                      "flops_per_launch": g_fl / g_n if g_n else None},
     }
 
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written, for scaling
+        # the FETCH_SIZE / WRITE_SIZE counters of the product kernel
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        del src, dst
+
     comps = {}
     if not args.no_comparators:
         def run(name, **kw):
@@ -234,6 +248,12 @@ def main():
         for name, dt in (("fp16", ipr.IPR_FP16), ("fp8_e4m3", ipr.IPR_FP8_E4M3),
                          ("bf16", ipr.IPR_BF16)):
             run(f"mixed_{name}_bulk_then_fp64", bulk_dtype=dt)
+        from paper_1703_02283_amd import train_start
+        theta = train_start.load_weights()
+        if theta is not None:
+            d = run("learned_start_fp64", init=ipr.IPR_INIT_LEARNED,
+                    mlp_params=torch.tensor(theta, device=dev))
+            out["speedup_learned_vs_identity"] = sec / d["seconds"]
     out["comparators"] = comps
 
     if not args.no_cpu:

@@ -52,7 +52,9 @@ typedef enum {
   IPR_INIT_IDENTITY = 0,  /* C_0 = (||A||_1 ||A||_inf)^{-1/(2p)} I: satisfies eq. (2) for every SPD A */
   IPR_INIT_PAPER_EQ3 = 1, /* eq. (3): C_0 = A^T / (||A||_1 ||A||_inf) */
   IPR_INIT_POLY = 2,      /* C_0 = s^{-1/p} (b0 I + b1 A/s + b2 (A/s)^2), s = sqrt(||A||_1 ||A||_inf) */
-  IPR_INIT_LEARNED = 3    /* POLY with (b0, b1, b2) predicted by the MLP in schedule.mlp_params */
+  IPR_INIT_LEARNED = 3    /* POLY in units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4}
+                             (>= lambda_max, one product), with (log b0, b1, b2) predicted by the
+                             MLP in schedule.mlp_params from ipr_features; checked against eq. (2) */
 } ipr_init;
 
 /* Arithmetic type of the bulk (early) iterations. FP64 refinement follows a
@@ -89,7 +91,9 @@ typedef struct {
   double residual_true;  /* ||I - C^p A||_F computed from C and A (NaN if not verified) */
   double init_bound;   /* sup over x in (0,1] of q(x)^p x for the start used (eq. (2) needs < 2) */
   double norm1, norminf; /* ||A||_1 and ||A||_inf */
-  double poly_used[3]; /* (b0, b1, b2) of the start used, in the POLY parametrisation */
+  double poly_used[3]; /* (b0, b1, b2) of the start used: C_0 = s^{-1/p} q(A/s) */
+  double init_scale;   /* that s: sqrt(||A||_1 ||A||_inf), or the certified bound
+                          (||A^2||_1 ||A^2||_inf)^{1/4} >= lambda_max for the learned start */
   double ms_norms, ms_init, ms_bulk, ms_refine, ms_verify; /* phase times (device events) */
   int gemm_launches;   /* products timed (schedule.timing = 1) */
   double ms_gemm;      /* their summed device time */
@@ -172,8 +176,12 @@ int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_byt
               hipStream_t stream);
 
 /* 16 features of each matrix of a packed batch (the learned start's input):
- * dFeat (device, batch x 16 float32). Definitions: see the feature table in
- * the design notes; all are O(n^2). offsets/n/p are host arrays. */
+ * dFeat (device, batch x 16 float32); offsets/n/p are host arrays, staged
+ * into dWork (>= 16 * batch + 1024 bytes). With s = sqrt(||A||_1 ||A||_inf),
+ * B = A/s, d = diag B, r_i = sum_j |B_ij|, o_i = r_i - |d_i|, t1 = trace B / n,
+ * t2 = ||B||_F^2 / n: log2(n)/10, p/4, t1, t2, log10 t1, log10 t2, t1^2/t2,
+ * min d, max d, log10 max(min d, 1e-30), min(d_i - o_i), mean r, sum o / sum|d|,
+ * max off-diagonal |B_ij|, std(d)/mean(d), log10 s. All O(n^2). */
 int ipr_features(const double* dA_packed, const int64_t* offsets, const int* n, const int* p,
                  int batch, float* dFeat, void* dWork, size_t work_bytes, hipStream_t stream);
 
@@ -189,6 +197,19 @@ int ipr_mlp_train_step(float* dParams, float* dGrad, float* dM, float* dV, const
                        const float* dT, int batch, int step, float lr, float* dLoss,
                        void* dWork, size_t work_bytes, hipStream_t stream);
 size_t ipr_mlp_workspace(int batch);
+
+/* Iteration counts of eq. (1) in exact arithmetic, per eigenvalue (the
+ * training labels of the learned start): for matrix i with eigenvalues
+ * dLam[offsets[i] .. offsets[i] + n[i]) (device, n[i] <= 2048), root p[i],
+ * scale scale[i] (host; s = sqrt(||A||_1 ||A||_inf)) and candidate start c
+ * (host cand[3c .. 3c+2] = b0, b1, b2 of C_0 = s^{-1/p} q(A/s)), counts the
+ * updates of the coupled iteration until the Frobenius residual is below tol;
+ * max_iter + 1 means not reached. counts: host, batch x ncand. With ncand = 0,
+ * cand holds one candidate per matrix (batch x 3) and counts has batch entries. */
+int ipr_spectral_counts(const double* dLam, const int64_t* offsets, const int* n, const int* p,
+                        const double* scale, int batch, const double* cand, int ncand, double tol,
+                        int max_iter, int* counts, void* dWork, size_t work_bytes,
+                        hipStream_t stream);
 
 /* Message describing the last error of the calling thread ("" if none). */
 const char* ipr_last_error(void);

@@ -14,5 +14,5 @@ from .binding import (  # noqa: F401
     ipr_schedule_default, ipr_workspace_size, ipr_solve, ipr_solve_batched, ipr_gemm,
     ipr_gemm_lowp, ipr_gemm_lowp_workspace, ipr_norms, ipr_features, ipr_mlp_forward,
     ipr_mlp_train_step, ipr_mlp_workspace, ipr_last_error, ipr_tune_batched,
-    ipr_get_batched_tiles, ipr_set_batched_tiles, IPR_BATCH_BUCKETS,
+    ipr_get_batched_tiles, ipr_set_batched_tiles, IPR_BATCH_BUCKETS, ipr_spectral_counts,
 )

@@ -32,7 +32,8 @@ class IprResult(ct.Structure):
                 ("fallback_used", ct.c_int), ("gemms", ct.c_int),
                 ("residual_proxy", ct.c_double), ("residual_true", ct.c_double),
                 ("init_bound", ct.c_double), ("norm1", ct.c_double), ("norminf", ct.c_double),
-                ("poly_used", ct.c_double * 3), ("ms_norms", ct.c_double),
+                ("poly_used", ct.c_double * 3), ("init_scale", ct.c_double),
+                ("ms_norms", ct.c_double),
                 ("ms_init", ct.c_double), ("ms_bulk", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_verify", ct.c_double), ("gemm_launches", ct.c_int), ("ms_gemm", ct.c_double),
                 ("gemm_flops", ct.c_double)]
@@ -83,6 +84,10 @@ _SIGS = {
     "ipr_mlp_workspace": (ct.c_size_t, [ct.c_int]),
     "ipr_last_error": (ct.c_char_p, []),
     "ipr_tune_batched": (ct.c_int, [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
+    "ipr_spectral_counts": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                       ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_double,
+                                       ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                                       ct.c_void_p]),
     "ipr_get_batched_tiles": (ct.c_int, [ct.c_void_p]),
     "ipr_set_batched_tiles": (ct.c_int, [ct.c_void_p]),
 }
@@ -151,7 +156,10 @@ def ipr_schedule_default(**overrides) -> IprSchedule:
         if k == "poly":
             s.poly = (ct.c_double * 3)(*v)
         elif k == "mlp_params":
+            if v is not None:
+                _need(v, torch.float32, (IPR_MLP_NPARAM,), "mlp_params")
             s.mlp_params = None if v is None else v.data_ptr()
+            s._mlp_ref = v  # the schedule holds only the pointer: keep the tensor alive
         else:
             setattr(s, k, v)
     return s
@@ -283,10 +291,36 @@ def ipr_features(A_packed, offsets, ns, ps, workspace=None, stream=None):
     nn = (ct.c_int * batch)(*[int(v) for v in ns])
     pp = (ct.c_int * batch)(*[int(v) for v in ps])
     feat = torch.empty((batch, 16), dtype=torch.float32, device=A_packed.device)
-    ws = workspace if workspace is not None else _workspace(8 * (4 * batch + 64), A_packed.device)
+    ws = workspace if workspace is not None else _workspace(16 * batch + 2048, A_packed.device)
     _check(_fn("ipr_features")(_ptr(A_packed), off, nn, pp, batch, _ptr(feat), _ptr(ws),
                                ws.numel(), _stream(stream)))
     return feat
+
+
+def ipr_spectral_counts(lam_packed, offsets, ns, ps, scales, cands, tol, max_iter=200,
+                        per_item=False, stream=None):
+    """Exact-arithmetic iteration counts (batch x ncand numpy int array) of the
+    coupled iteration per eigenvalue for candidate polynomial starts."""
+    import numpy as np
+    _need(lam_packed, torch.float64, name="lam_packed")
+    batch = len(ns)
+    cand = np.ascontiguousarray(np.asarray(cands, dtype=np.float64).reshape(-1, 3))
+    ncand = 0 if per_item else cand.shape[0]
+    if per_item and cand.shape[0] != batch:
+        raise ValueError("per_item needs one candidate per matrix")
+    off = (ct.c_int64 * batch)(*[int(o) for o in offsets])
+    nn = (ct.c_int * batch)(*[int(v) for v in ns])
+    pp = (ct.c_int * batch)(*[int(v) for v in ps])
+    sc = (ct.c_double * batch)(*[float(v) for v in scales])
+    cc = cand.ctypes.data_as(ct.c_void_p)
+    out = np.zeros((batch, max(ncand, 1)), dtype=np.int32)
+    nc = max(ncand, batch if per_item else 1)
+    ws = _workspace(batch * (16 + 8) + 24 * nc + 4 * batch * max(ncand, 1) + 8192,
+                    lam_packed.device)
+    _check(_fn("ipr_spectral_counts")(_ptr(lam_packed), off, nn, pp, sc, batch, cc, ncand,
+                                      float(tol), int(max_iter), out.ctypes.data_as(ct.c_void_p),
+                                      _ptr(ws), ws.numel(), _stream(stream)))
+    return out[:, 0] if per_item else out
 
 
 def ipr_mlp_forward(params, X, stream=None):

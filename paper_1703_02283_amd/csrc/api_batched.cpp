@@ -250,6 +250,7 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
       r.norm1 = res[i].norm1;
       r.norminf = res[i].norminf;
       r.init_bound = 1.0;
+      r.init_scale = std::sqrt(res[i].norm1 * res[i].norminf);
       r.poly_used[0] = 1.0;
     }
     if (res[i].status != IPR_OK && status == IPR_OK) status = res[i].status;

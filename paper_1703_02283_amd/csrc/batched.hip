@@ -158,6 +158,15 @@ __device__ double wg_tile(const double* __restrict__ L, const double* __restrict
           for (int b = 0; b < FB; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
+      if constexpr (FB == 1) {
+        // With one 16 x 16 block per wave no independent instruction follows
+        // the slab's last FP64 MFMA. On gfx950 that instruction takes 16
+        // passes, so a vector read of its result needs 19 wait states; the
+        // compiler's hazard padding on the loop's exit path is shorter (9),
+        // and the last-written accumulator lanes were read stale. Pad here,
+        // with the accumulator tied so that no read is hoisted above the pad.
+        asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+a"(acc[0][0]));
+      }
     } else {
       // The bf16 16x16x32 operand spans 32 k and a slab holds 16: lanes whose
       // k is 16..31 supply zeros (half of the instruction's k width idles).

@@ -161,6 +161,19 @@ __global__ __launch_bounds__(NT) void symmetrize_kernel(double* __restrict__ X, 
   }
 }
 
+// Y = a0 I + a1 A + a2 G.
+__global__ __launch_bounds__(NT) void lincomb_kernel(const double* __restrict__ A,
+                                                      const double* __restrict__ G, int n,
+                                                      double a0, double a1, double a2,
+                                                      double* __restrict__ Y) {
+  const size_t total = (size_t)n * n;
+  for (size_t t = (size_t)blockIdx.x * NT + threadIdx.x; t < total;
+       t += (size_t)gridDim.x * NT) {
+    const size_t i = t / n, j = t - i * n;
+    Y[t] = (i == j ? a0 : 0.0) + a1 * A[t] + (G ? a2 * G[t] : 0.0);
+  }
+}
+
 int grid_for(size_t count) {
   size_t g = (count + NT - 1) / NT;
   if (g > 65536) g = 65536;
@@ -200,6 +213,13 @@ hipError_t reduce_fro(const double* slots, int count, double* out, hipStream_t s
 hipError_t affine(const double* X, int n, double a, double b, double* Y, hipStream_t stream) {
   hipLaunchKernelGGL(affine_kernel, dim3(grid_for((size_t)n * n)), dim3(NT), 0, stream, X, n, a, b,
                      Y);
+  return hipGetLastError();
+}
+
+hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1, double a2,
+                   double* Y, hipStream_t stream) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for((size_t)n * n)), dim3(NT), 0, stream, A, G, n,
+                     a0, a1, a2, Y);
   return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@
 //    global load is a fully coalesced row segment and neither operand needs a
 //    transpose on its way into LDS. Every left operand of the iteration is
 //    symmetric, so L^T R = L R there.
-//  * K slabs of 16 double-buffered in LDS (one barrier per slab); the row pitch
+//  * K slabs of 32 double-buffered in LDS (one barrier per slab; 144 KiB, one
+//    workgroup per CU); the row pitch
 //    of 144 doubles puts consecutive k rows half a bank sweep apart, so the
 //    16-lane row reads of the MFMA operands are conflict free.
 //  * XCD-aware tile order: workgroup w runs on XCD w % 8, so w is remapped to
@@ -36,14 +37,15 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;        // tile edge (rows = cols)
-constexpr int BK = 16;         // k slab per LDS stage
+constexpr int BK = 32;         // k slab per LDS stage
 constexpr int WM = 64;         // wave tile rows
 constexpr int WN = 32;         // wave tile columns
 constexpr int FM = WM / 16;    // 16 x 16 blocks per wave, rows
 constexpr int FN = WN / 16;    // 16 x 16 blocks per wave, columns
 constexpr int LDP = BM + 16;   // LDS row pitch in doubles
 constexpr int NT = 512;        // threads per workgroup (8 waves)
-constexpr int FLUSH = 4;       // slabs (4 x 16 = 64 k) per slab accumulator
+constexpr int FLUSH = 2;       // slabs (2 x 32 = 64 k) per slab accumulator
+constexpr int NQ = BK / 8;     // loader passes (8 rows of 128 per pass)
 
 __global__ __launch_bounds__(NT, 1)
 void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R, int n,
@@ -74,24 +76,24 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
       sum[a][b] = slab[a][b];
     }
 
-  // Loader: 16 rows x 128 columns per operand = 1024 double2; thread t moves
-  // rows (t / 64) + 8q, q = 0..1, columns 2 (t % 64) and 2 (t % 64) + 1.
+  // Loader: 32 rows x 128 columns per operand = 2048 double2; thread t moves
+  // rows (t / 64) + 8q, q = 0..3, columns 2 (t % 64) and 2 (t % 64) + 1.
   const int lrow = tid >> 6;
   const int lcol = (tid & 63) * 2;
   const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
-  double2 la[2], ra[2];
+  double2 la[NQ], ra[NQ];
 
   auto gload = [&](int k0) {
     if (cols_in && k0 + BK <= n) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const size_t row = (size_t)(k0 + lrow + 8 * q) * n;
         la[q] = *reinterpret_cast<const double2*>(L + row + i0 + lcol);
         ra[q] = *reinterpret_cast<const double2*>(R + row + j0 + lcol);
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const int k = k0 + lrow + 8 * q;
         const size_t row = (size_t)k * n;
         const bool kin = k < n;
@@ -104,7 +106,7 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       *reinterpret_cast<double2*>(&Ls[buf][lrow + 8 * q][lcol]) = la[q];
       *reinterpret_cast<double2*>(&Rs[buf][lrow + 8 * q][lcol]) = ra[q];
     }

@@ -58,6 +58,10 @@ hipError_t affine(const double* X, int n, double a, double b, double* Y,
 
 hipError_t copy(const double* X, size_t count, double* Y, hipStream_t stream);
 
+// Y = a0 I + a1 A + a2 G (G may be null).
+hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1, double a2,
+                   double* Y, hipStream_t stream);
+
 // X <- (X + X^T) / 2 in place.
 hipError_t symmetrize(double* X, int n, hipStream_t stream);
 

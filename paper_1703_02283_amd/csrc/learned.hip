@@ -58,12 +58,13 @@ __device__ double block_red(double v, int op, double* sh) {
 __global__ __launch_bounds__(NT) void features_kernel(const double* __restrict__ Apack,
                                                        const int64_t* __restrict__ off,
                                                        const int* __restrict__ ns,
-                                                       const int* __restrict__ ps,
-                                                       float* __restrict__ feat) {
+                                                       const int* __restrict__ ps, int n_one,
+                                                       int p_one, float* __restrict__ feat) {
   __shared__ double sh[NT / 64];
   const int m = blockIdx.x;
-  const int n = ns[m];
-  const double* A = Apack + off[m];
+  const int n = ns ? ns[m] : n_one;           // one matrix: n, p passed by value
+  const int pm = ps ? ps[m] : p_one;
+  const double* A = Apack + (off ? off[m] : 0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // ||A||_1: column sums
   double cmax = 0.0;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(NT) void features_kernel(const double* __restrict__
     const double var_d = fmax(sd2 / n - mean_d * mean_d, 0.0);
     float* f = feat + (size_t)m * NI;
     f[0] = (float)(log2((double)n) / 10.0);
-    f[1] = (float)(ps[m] / 4.0);
+    f[1] = (float)(pm / 4.0);
     f[2] = (float)t1;
     f[3] = (float)t2;
     f[4] = (float)log10(t1);
@@ -295,7 +296,9 @@ __global__ __launch_bounds__(NT) void spectral_counts_kernel(
   const int m = blockIdx.y, ci = blockIdx.x;
   const int n = ns[m], p = ps[m];
   const double s = scale[m];
-  const double b0 = cand[3 * ci], b1 = cand[3 * ci + 1], b2 = cand[3 * ci + 2];
+  // ncand == 0: one candidate per matrix (cand[3 m ..]), else a shared list
+  const double* cc = ncand ? cand + 3 * ci : cand + 3 * m;
+  const double b0 = cc[0], b1 = cc[1], b2 = cc[2];
   // each thread keeps up to 8 eigenvalues (n <= 2048)
   double x[8], y[8];  // x = lambda / s, y = q(x)^p x = current eigenvalue of M
   int cnt = 0;
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(NT) void spectral_counts_kernel(
       y[t] = pow(nf, p) * y[t];
     }
   }
-  if (threadIdx.x == 0) counts[(size_t)m * ncand + ci] = k;
+  if (threadIdx.x == 0) counts[(size_t)m * (ncand ? ncand : 1) + ci] = k;
   (void)x;
 }
 
@@ -331,7 +334,14 @@ int mlp_nparam() { return NPARAM; }
 
 hipError_t features(const double* Apack, const int64_t* off, const int* ns, const int* ps,
                     int batch, float* feat, hipStream_t stream) {
-  hipLaunchKernelGGL(features_kernel, dim3(batch), dim3(NT), 0, stream, Apack, off, ns, ps, feat);
+  hipLaunchKernelGGL(features_kernel, dim3(batch), dim3(NT), 0, stream, Apack, off, ns, ps, 0, 0,
+                     feat);
+  return hipGetLastError();
+}
+
+hipError_t features_one(const double* A, int n, int p, float* feat, hipStream_t stream) {
+  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NT), 0, stream, A, nullptr, nullptr, nullptr,
+                     n, p, feat);
   return hipGetLastError();
 }
 
@@ -361,8 +371,8 @@ hipError_t mlp_train_step(float* params, float* grad, float* m, float* v, const 
 hipError_t spectral_counts(const double* lam, const int64_t* off, const int* ns, const int* ps,
                            const double* scale, const double* cand, int ncand, int batch,
                            double tol, int max_iter, int* counts, hipStream_t stream) {
-  hipLaunchKernelGGL(spectral_counts_kernel, dim3(ncand, batch), dim3(NT), 0, stream, lam, off, ns,
-                     ps, scale, cand, ncand, tol, max_iter, counts);
+  hipLaunchKernelGGL(spectral_counts_kernel, dim3(ncand ? ncand : 1, batch), dim3(NT), 0, stream,
+                     lam, off, ns, ps, scale, cand, ncand, tol, max_iter, counts);
   return hipGetLastError();
 }
 

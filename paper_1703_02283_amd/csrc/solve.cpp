@@ -27,6 +27,7 @@
 #include "../../include/ipr.h"
 #include "ipr_host.h"
 #include "ipr_internal.h"
+#include "learned.h"
 #include "lowp.h"
 
 namespace ipr {
@@ -463,8 +464,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     return fail(IPR_EARG, "ipr_solve: unknown init %d", s.init);
   if (s.bulk_dtype < IPR_FP64 || s.bulk_dtype > IPR_FP8_E4M3)
     return fail(IPR_EARG, "ipr_solve: unknown bulk dtype %d", s.bulk_dtype);
-  if (s.init == IPR_INIT_LEARNED)
-    return fail(IPR_EARG, "ipr_solve: learned start is not available in this build");
+  if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
+    return fail(IPR_EARG, "ipr_solve: the learned start needs schedule.mlp_params");
 
   Solver sv;
   bool ok;
@@ -507,8 +508,11 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   if (!(s2 > 0.0) || !std::isfinite(s2))
     return fail(IPR_EARG, "ipr_solve: A has zero or non-finite norm");
 
-  // ---- start C_0 (as sigma^{-1/p} q(A/sigma)) and R_0 = I - C_0^p A
+  // ---- start C_0 = sc^{-1/p} q(A / sc), q(x) = b0 + b1 x + b2 x^2, with the
+  // spectrum of A / sc inside (0, 1]; then M_0 = C_0^p A and N_0.
   double b[3] = {1.0, 0.0, 0.0};
+  double sc = sigma;            // ||A||_2 <= sqrt(||A||_1 ||A||_inf)
+  const double* G = nullptr;    // A^2 when the learned start computed it
   int init = s.init;
   if (init == IPR_INIT_POLY) {
     for (int i = 0; i < 3; ++i) b[i] = s.poly[i];
@@ -516,40 +520,81 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     // A / sigma^2 = sigma^{-1/p} q(A / sigma) with q(x) = sigma^{1/p - 1} x
     b[0] = 0.0;
     b[1] = std::pow(sigma, 1.0 / p - 1.0);
+  } else if (init == IPR_INIT_LEARNED) {
+    // Certified scale: lambda_max(A)^2 = lambda_max(A^2) <= sqrt(||A^2||_1 ||A^2||_inf),
+    // one triangle product; then the network's polynomial in units of that bound.
+    double* Gm = sv.Mb[1];  // free until the first iteration
+    Epilogue e;
+    e.D = Gm;
+    HIP_TRY(sv.prod.f64(dA, dA, 1, e));
+    HIP_TRY(norms_1_inf(Gm, n, w.norms_scratch, w.scal + 2, stream));
+    float* feat = reinterpret_cast<float*>(w.scal + 16);   // 16 floats
+    float* yout = reinterpret_cast<float*>(w.scal + 24);   // 3 floats
+    HIP_TRY(features_one(dA, n, p, feat, stream));
+    HIP_TRY(mlp_forward(s.mlp_params, feat, 1, yout, nullptr, nullptr, stream));
+    double hs[32];
+    if (int rc = read_scalars(w.scal, 32, hs, stream)) return rc;
+    float y[3];
+    std::memcpy(y, &hs[24], sizeof y);
+    // rounding of the computed A^2 is below n u relative; keep a margin of 8 n u
+    const double bound = std::sqrt(std::sqrt(hs[2] * hs[3])) *
+                         (1.0 + 8.0 * n * std::numeric_limits<double>::epsilon());
+    if (std::isfinite(bound) && bound > 0.0) sc = std::min(sigma, bound);
+    G = Gm;
+    b[0] = std::exp((double)y[0]);
+    b[1] = (double)y[1];
+    b[2] = (double)y[2];
+    if (!std::isfinite(b[0]) || !std::isfinite(b[1]) || !std::isfinite(b[2])) b[0] = -1.0;
+    // polynomial terms cost p products: use them only when the network asks
+    // for them (beyond 5% of b0)
+    if (std::fabs(b[1]) < 0.05 * b[0] && std::fabs(b[2]) < 0.05 * b[0]) b[1] = b[2] = 0.0;
+    res.init_scale = sc;
   }
   double sup_phi;
   int q_pos;
   poly_guard(b, p, &sup_phi, &q_pos);
+  if (init == IPR_INIT_LEARNED && q_pos && std::isfinite(sup_phi) && sup_phi >= 2.0) {
+    // A prediction beyond eq. (2): q -> t q scales q^p x by t^p, so t with
+    // t^p sup = 1.98 brings it back inside (q > 0 is unchanged).
+    const double t = std::pow(1.98 / sup_phi, 1.0 / p);
+    for (double& v : b) v *= t;
+    poly_guard(b, p, &sup_phi, &q_pos);
+  }
   if (!(q_pos && sup_phi < 2.0)) {
     if (!s.guard_fallback)
       return fail(IPR_EGUARD, "ipr_solve: start violates eq. (2) (sup q^p x = %g)", sup_phi);
     res.fallback_used = 1;
     init = IPR_INIT_IDENTITY;
+    sc = sigma;
     b[0] = 1.0;
     b[1] = b[2] = 0.0;
     poly_guard(b, p, &sup_phi, &q_pos);
   }
   res.init_bound = sup_phi;
   for (int i = 0; i < 3; ++i) res.poly_used[i] = b[i];
+  if (res.init_scale == 0.0) res.init_scale = sc;
 
-  const double root = std::pow(sigma, -1.0 / p);
-  if (init == IPR_INIT_IDENTITY) {
-    HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(), sv.M(),
+  const double root = std::pow(sc, -1.0 / p);
+  if (b[1] == 0.0 && b[2] == 0.0) {
+    // scaled identity c I, c = b0 sc^{-1/p}: M_0 = c^p A elementwise
+    const double c = b[0] * root;
+    HIP_TRY(init_identity(dA, n, p, c, std::pow(b[0], (double)p) / sc, sv.C(), sv.M(),
                           sv.Nb[sv.ni], w.partial, stream));
     sv.slots = n;
     if (int rc = sv.reduce()) return rc;
   } else {
-    if (b[2] != 0.0) {
-      Epilogue e;
-      e.alpha = root * b[2] / s2;
-      e.beta = root * b[1] / sigma;
+    if (b[2] != 0.0 && !G) {
+      Epilogue e;  // C_0 from one product A A
+      e.alpha = root * b[2] / (sc * sc);
+      e.beta = root * b[1] / sc;
       e.X = dA;
       e.gamma = root * b[0];
       e.D = sv.C();
       HIP_TRY(sv.prod(dA, dA, sv.tri, e));
       if (!sv.tri) HIP_TRY(symmetrize(sv.C(), n, stream));
     } else {
-      HIP_TRY(affine(dA, n, root * b[1] / sigma, root * b[0], sv.C(), stream));
+      HIP_TRY(lincomb(dA, G, n, root * b[0], root * b[1] / sc, root * b[2] / (sc * sc), sv.C(),
+                      stream));
     }
     // M_0 = C_0^p A: products of polynomials in A, symmetric
     if (int rc = sv.power_chain(sv.C(), dA, sv.M(), sv.Nb[sv.ni], sv.tri)) return rc;

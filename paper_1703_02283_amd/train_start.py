@@ -1,0 +1,331 @@
+"""Training and evaluation of the learned start (weights: start_mlp.npz).
+
+    python -m paper_1703_02283_amd.train_start --train 200000 --heldout 10000
+
+The start C_0 = s^{-1/p} q(A/s), q(x) = b0 + b1 x + b2 x^2, is expressed in
+units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4} >= lambda_max,
+so the spectrum of A/s lies in (0, 1] and eq. (2) is checked on that interval.
+The network (16 -> 64 -> 64 -> 3, GELU) maps ipr_features(A) to
+(log b0, b1, b2).
+
+Data: SPD matrices A = Q diag(lam) Q^T with Haar Q, n ~ U{64..1024},
+p ~ U{1..4}, kappa log-uniform in [10, 1e6] (seeds 1e6 + i for training,
+2e6 + i held out). The matrices are drawn on the GPU with torch (QR of Gaussian
+matrices, grouped by order); features, labels, training and inference all run
+in libipr's kernels:
+  * labels: for every matrix, ipr_spectral_counts gives the exact-arithmetic
+    iteration count of the method itself for each candidate start; the label
+    is the candidate with the fewest matrix products in total (the scale
+    bound's product, p more when q is not constant, p + 1 per iteration);
+  * training: ipr_mlp_train_step (forward, backward, Adam on the GPU).
+Feature standardisation is folded into the first layer after training, so the
+stored network reads raw features.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as ipr
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "start_mlp.npz")
+NPARAM = ipr.IPR_MLP_NPARAM
+TOL = 1e-10
+MAXIT = 200
+
+
+def log(*a):
+    print("[train_start]", *a, file=sys.stderr, flush=True)
+
+
+def recipe(count, base_seed, n_range=(64, 1024), p_range=(1, 4), kappa_range=(10.0, 1e6)):
+    """(n, p, kappa, seed) per item; same draws as workloads.training_recipe."""
+    out = []
+    for i in range(count):
+        s = base_seed + i
+        rng = np.random.default_rng(s)
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        p = int(p_range[0] + int(rng.integers(0, p_range[1] - p_range[0] + 1)))
+        kappa = float(np.exp(rng.uniform(np.log(kappa_range[0]), np.log(kappa_range[1]))))
+        out.append((n, p, kappa, s))
+    return out
+
+
+def spectrum(n, kappa, seed):
+    """lam log-uniform on [1/kappa, 1], both ends pinned (host, seeded)."""
+    rng = np.random.default_rng(seed + 7_919)
+    lam = np.exp(rng.uniform(np.log(1.0 / kappa), 0.0, n))
+    if n >= 2:
+        lam[0], lam[1] = 1.0 / kappa, 1.0
+    return lam
+
+
+def make_group(items, device):
+    """Matrices of one order n: Haar Q by QR of seeded Gaussians (batched on
+    the GPU), A = Q diag(lam) Q^T symmetrised. Returns (A [b, n, n], lam list)."""
+    n = items[0][0]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(items[0][3])
+    g = torch.randn((len(items), n, n), dtype=torch.float64, device=device, generator=gen)
+    q, r = torch.linalg.qr(g)
+    d = torch.sign(torch.diagonal(r, dim1=-2, dim2=-1))
+    d[d == 0] = 1.0
+    q = q * d.unsqueeze(-2)
+    lams = [spectrum(n, kappa, seed) for (_, _, kappa, seed) in items]
+    lam_t = torch.tensor(np.stack(lams), dtype=torch.float64, device=device)
+    a = (q * lam_t.unsqueeze(-2)) @ q.transpose(-1, -2).contiguous()
+    a = 0.5 * (a + a.transpose(-1, -2))
+    return a.contiguous(), lams
+
+
+def guard_ok(b, p):
+    """0 < q(x) and q(x)^p x < 2 on (0, 1] (eq. (2) for the spectrum in (0, 1])."""
+    x = np.linspace(0.0, 1.0, 4001)[1:]
+    q = b[0] + b[1] * x + b[2] * x * x
+    return bool(np.all(q > 0) and np.all(q ** p * x < 2.0 * (1 - 1e-6)))
+
+
+def candidates(p):
+    """Candidate starts of the label search, all satisfying eq. (2) on (0, 1]."""
+    out = []
+    for b0 in np.geomspace(0.5, 2.0 ** (1.0 / p) * 0.999, 28):
+        out.append((b0, 0.0, 0.0))
+        for t in (0.25, 0.5, 0.75):
+            out.append((b0, -t * b0, 0.0))
+    return np.array([c for c in out if guard_ok(c, p)])
+
+
+def build_dataset(items, device, chunk=256):
+    """Features (float32), scales, labels (log b0, b1, b2) and the identity
+    start's iteration count for every item."""
+    order = {}
+    for k, it in enumerate(items):
+        order.setdefault(it[0], []).append(k)
+    m = len(items)
+    feats = np.zeros((m, 16), np.float32)
+    labels = np.zeros((m, 3), np.float32)
+    scales = np.zeros(m)
+    sigmas = np.zeros(m)
+    best_products = np.zeros(m)
+    ident_products = np.zeros(m)
+    cands = {p: candidates(p) for p in (1, 2, 3, 4)}
+    t0 = time.time()
+    done = 0
+    for n, idx in sorted(order.items()):
+        for c0 in range(0, len(idx), chunk):
+            sel = idx[c0:c0 + chunk]
+            its = [items[k] for k in sel]
+            a, lams = make_group(its, device)
+            b = len(its)
+            flat = a.reshape(-1)
+            offs = [j * n * n for j in range(b)]
+            ns = [n] * b
+            ps = [it[1] for it in its]
+            f = ipr.ipr_features(flat, offs, ns, ps)
+            feats[sel] = f.cpu().numpy()
+            # certified scale and the norm scale
+            absa = a.abs()
+            n1 = absa.sum(-2).amax(-1)
+            ni = absa.sum(-1).amax(-1)
+            a2 = torch.matmul(a, a).abs()
+            g1 = a2.sum(-2).amax(-1)
+            gi = a2.sum(-1).amax(-1)
+            sig = torch.sqrt(n1 * ni).cpu().numpy()
+            bound = torch.sqrt(torch.sqrt(g1 * gi)).cpu().numpy() * (1 + 8 * n * 2.2e-16)
+            sc = np.minimum(sig, bound)
+            scales[sel] = sc
+            sigmas[sel] = sig
+            lam_flat = torch.tensor(np.concatenate(lams), dtype=torch.float64, device=device)
+            loffs = [j * n for j in range(b)]
+            for pv in sorted(set(ps)):
+                sub = [j for j in range(b) if ps[j] == pv]
+                cc = cands[pv]
+                cnt = ipr.ipr_spectral_counts(
+                    lam_flat, [loffs[j] for j in sub], [n] * len(sub), [pv] * len(sub),
+                    [sc[j] for j in sub], cc, TOL, MAXIT)
+                extra = np.where((cc[:, 1] != 0) | (cc[:, 2] != 0), pv, 0)
+                cost = 1 + extra[None, :] + (pv + 1) * cnt
+                k = np.argmin(cost, axis=1)
+                ident = ipr.ipr_spectral_counts(
+                    lam_flat, [loffs[j] for j in sub], [n] * len(sub), [pv] * len(sub),
+                    [sig[j] for j in sub], np.array([[1.0, 0.0, 0.0]]), TOL, MAXIT)[:, 0]
+                for r, j in enumerate(sub):
+                    gj = sel[j]
+                    bb = cc[k[r]]
+                    labels[gj] = (math.log(bb[0]), bb[1], bb[2])
+                    best_products[gj] = cost[r, k[r]]
+                    ident_products[gj] = (pv + 1) * ident[r]
+            done += b
+            del a
+        log(f"n={n}: {done}/{m} items, {time.time() - t0:.0f} s")
+    return dict(feats=feats, labels=labels, scales=scales, sigmas=sigmas,
+                best_products=best_products, ident_products=ident_products)
+
+
+def init_params(rng):
+    sizes = (16, 64, 64, 3)
+    parts = []
+    for i in range(3):
+        fi, fo = sizes[i], sizes[i + 1]
+        parts.append(rng.standard_normal(fo * fi) * math.sqrt(2.0 / fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fold_standardisation(theta, mu, sd):
+    """First layer reading standardised x' = (x - mu) / sd -> reading raw x."""
+    th = theta.copy()
+    w1 = th[:64 * 16].reshape(64, 16)
+    b1 = th[64 * 16:64 * 16 + 64]
+    w1n = w1 / sd[None, :]
+    b1n = b1 - w1n @ mu
+    th[:64 * 16] = w1n.ravel()
+    th[64 * 16:64 * 16 + 64] = b1n
+    return th
+
+
+def train(data, device, epochs=30, batch=1024, lr=2e-3, seed=0):
+    x = data["feats"].astype(np.float64)
+    mu = x.mean(0)
+    sd = x.std(0) + 1e-6
+    xs = ((x - mu) / sd).astype(np.float32)
+    X = torch.tensor(xs, device=device)
+    T = torch.tensor(data["labels"], device=device)
+    rng = np.random.default_rng(seed)
+    theta = torch.tensor(init_params(rng), device=device)
+    grad = torch.zeros_like(theta)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    loss = torch.zeros(1, device=device)
+    ws = torch.empty(ipr.ipr_mlp_workspace(batch), dtype=torch.uint8, device=device)
+    nb = len(xs) // batch
+    step = 0
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(len(xs)), device=device)
+        tot = 0.0
+        for bi in range(nb):
+            sel = perm[bi * batch:(bi + 1) * batch]
+            xb = X[sel].contiguous()
+            tb = T[sel].contiguous()
+            step += 1
+            lr_t = lr * (0.5 * (1 + math.cos(math.pi * step / (epochs * nb))))
+            ipr.ipr_mlp_train_step(theta, grad, m, v, xb, tb, step, max(lr_t, 1e-5), loss,
+                                   workspace=ws)
+            tot += float(loss.item()) if bi % 50 == 0 else 0.0
+        log(f"epoch {ep}: loss {loss.item():.4e}")
+    th = fold_standardisation(theta.cpu().numpy().astype(np.float64), mu, sd)
+    return th.astype(np.float32), float(loss.item())
+
+
+def predict(theta, feats, device):
+    y = ipr.ipr_mlp_forward(torch.tensor(theta, device=device),
+                            torch.tensor(feats, device=device).contiguous())
+    return y.cpu().numpy()
+
+
+def project(b, p):
+    """The start the solver uses for a prediction: polynomial terms below 5%
+    of b0 dropped, then scaled into eq. (2)'s set when it overshoots."""
+    b = np.array(b, dtype=np.float64)
+    if abs(b[1]) < 0.05 * b[0] and abs(b[2]) < 0.05 * b[0]:
+        b[1] = b[2] = 0.0
+    x = np.linspace(0.0, 1.0, 4001)[1:]
+    q = b[0] + b[1] * x + b[2] * x * x
+    if np.all(q > 0):
+        sup = float(np.max(q ** p * x))
+        if sup >= 2.0:
+            b = b * (1.98 / sup) ** (1.0 / p)
+    return b
+
+
+def evaluate(theta, items, data, device):
+    """Iterations and products of the learned start against the scaled
+    identity, exact arithmetic (ipr_spectral_counts) on held-out items."""
+    y = predict(theta, data["feats"], device)
+    ps = np.array([it[1] for it in items])
+    b = np.stack([project((np.exp(y[k, 0]), y[k, 1], y[k, 2]), ps[k])
+                  for k in range(len(items))])
+    ok = np.array([np.all(np.isfinite(b[k])) and guard_ok(b[k], ps[k])
+                   for k in range(len(items))])
+    res = {"fallback_rate": float(1 - ok.mean())}
+    learned_products = np.where(ok, 0.0, np.nan)
+    # group by n for the count kernel
+    order = {}
+    for k, it in enumerate(items):
+        order.setdefault(it[0], []).append(k)
+    iters_l = np.zeros(len(items))
+    iters_i = data["ident_products"] / (ps + 1)
+    for n, idx in sorted(order.items()):
+        lams = [spectrum(n, items[k][2], items[k][3]) for k in idx]
+        lam_flat = torch.tensor(np.concatenate(lams), dtype=torch.float64, device=device)
+        bb = np.where(ok[idx, None], b[idx], np.array([1.0, 0.0, 0.0]))
+        sc = np.where(ok[idx], data["scales"][idx], data["sigmas"][idx])
+        cnt = ipr.ipr_spectral_counts(lam_flat, [j * n for j in range(len(idx))], [n] * len(idx),
+                                      [int(ps[k]) for k in idx], list(sc), bb, TOL, MAXIT,
+                                      per_item=True)
+        iters_l[idx] = cnt
+    extra = np.where(ok, 1 + np.where((b[:, 1] != 0) | (b[:, 2] != 0), ps, 0), 0)
+    learned_products = extra + (ps + 1) * iters_l
+    res.update({
+        "items": len(items),
+        "mean_iterations_identity": float(iters_i.mean()),
+        "mean_iterations_learned": float(iters_l.mean()),
+        "mean_products_identity": float(data["ident_products"].mean()),
+        "mean_products_learned": float(learned_products.mean()),
+        "mean_products_best_candidate": float(data["best_products"].mean()),
+        "products_saved_fraction": float(1 - learned_products.mean() / data["ident_products"].mean()),
+        "not_converged_learned": int((iters_l > MAXIT).sum()),
+    })
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=200000)
+    ap.add_argument("--heldout", type=int, default=10000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args()
+    ipr.load()
+    device = torch.device("cuda:0")
+    t0 = time.time()
+    tr_items = recipe(args.train, 10**6)
+    ho_items = recipe(args.heldout, 2 * 10**6)
+    log("building training set")
+    tr = build_dataset(tr_items, device)
+    log("building held-out set")
+    ho = build_dataset(ho_items, device)
+    t1 = time.time()
+    theta, final_loss = train(tr, device, epochs=args.epochs)
+    t2 = time.time()
+    report = {"train_items": len(tr_items), "heldout_items": len(ho_items),
+              "final_loss": final_loss, "seconds_data": t1 - t0, "seconds_train": t2 - t1,
+              "train": evaluate(theta, tr_items[:min(len(tr_items), 20000)],
+                                {k: v[:20000] for k, v in tr.items()}, device),
+              "heldout": evaluate(theta, ho_items, ho, device)}
+    np.savez(args.out, theta=theta, report=json.dumps(report))
+    log(json.dumps(report, indent=1))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+
+
+def load_weights(path=WEIGHTS):
+    """The stored network parameters (float32, IPR_MLP_NPARAM) or None."""
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return z["theta"].astype(np.float32)
+
+
+if __name__ == "__main__":
+    main()
