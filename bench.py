@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (vendor figure)
+# dense matrix-core peaks of the bulk dtypes (vendor figures, no sparsity)
+PEAK_LP_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp8_e4m3": 5000.0}
 
 
 def log(*a):
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the kernel-matrix and batched workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -105,6 +109,96 @@ def _cpu_model():
     except Exception:
         pass
     return None
+
+
+def solve_record(ipr, r, seconds, dtype_name=None):
+    d = {"seconds": seconds, "status": ipr.binding.STATUS_NAMES[r.status],
+         "iters_bulk": r.iters_bulk, "iters_fp64": r.iters_fp64, "gemms": r.gemms,
+         "fallback_used": r.fallback_used, "residual_true": r.residual_true,
+         "fp64_tflops": (r.gemm_flops / (r.ms_gemm * 1e-3) / 1e12) if r.ms_gemm else None}
+    if r.lp_gemm_launches:
+        lp = r.lp_gemm_flops / (r.ms_lp_gemm * 1e-3) / 1e12 if r.ms_lp_gemm else None
+        d["lp_gemm_launches"] = r.lp_gemm_launches
+        d["lp_tflops"] = lp
+        if lp and dtype_name in PEAK_LP_TFLOPS:
+            d["lp_frac_of_peak"] = lp / PEAK_LP_TFLOPS[dtype_name]
+    return d
+
+
+def kernel_matrix_runs(ipr, torch, w, dev, tol):
+    """The Gaussian-kernel Gram matrix, n = 4096: plain FP64 against a bf16
+    bulk phase with FP64 refinement, p = 1, 2, 3."""
+    n = 4096
+    A = torch.from_numpy(w.kernel_matrix(n, seed=0)).to(dev)
+    C = torch.empty_like(A)
+    out = {"workload": "kernel_matrix n=4096 (points uniform in a box of side 20, length 1, "
+                       "shift 1e-3) seed=0", "tol": tol}
+    for p in (1, 2, 3):
+        row = {}
+        ref = None
+        for name, dt in (("fp64", ipr.IPR_FP64), ("bf16_bulk_then_fp64", ipr.IPR_BF16)):
+            s = ipr.ipr_schedule_default(timing=1, bulk_dtype=dt)
+            ws = torch.empty(ipr.ipr_workspace_size(n, p, 1, s), dtype=torch.uint8, device=dev)
+            ipr.ipr_solve(A, p, tol, schedule=s, out=C, workspace=ws)   # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, workspace=ws)
+            torch.cuda.synchronize()
+            row[name] = solve_record(ipr, r, time.perf_counter() - t, "bf16")
+            if ref is None:
+                ref = C.clone()
+            else:
+                row[name]["rel_fro_vs_fp64"] = float(torch.linalg.norm(C - ref) /
+                                                     torch.linalg.norm(ref))
+            log(f"kernel_matrix p={p} {name}", json.dumps(row[name]))
+        out[f"p{p}"] = row
+    return out
+
+
+def batched_runs(ipr, torch, w, dev, tol, reps=3):
+    """2000 independent problems, n ~ U{32..512}, p in {1, 2, 4}, kappa
+    log-uniform in [10, 1e5]: one captured launch per call."""
+    import numpy as np
+    items = w.batch_recipe(2000)
+    mats = [w.batch_matrix(n, kappa, seed)[0] for (n, _, kappa, seed) in items]
+    ns = [it[0] for it in items]
+    ps = [it[1] for it in items]
+    offs, tot = [], 0
+    for a in mats:
+        offs.append(tot)
+        tot += a.size
+    buf = np.empty(tot)
+    for o, a in zip(offs, mats):
+        buf[o:o + a.size] = a.ravel()
+    A = torch.from_numpy(buf).to(dev)
+    C = torch.empty_like(A)
+    out = {"workload": "batch_recipe(2000): n ~ U{32..512}, p in {1,2,4}, "
+                       "kappa logU[10,1e5], seeds 1000+i", "tol": tol,
+           "matrices": len(ns), "elements": tot}
+    for name, dt in (("fp64", ipr.IPR_FP64), ("bf16_bulk_then_fp64", ipr.IPR_BF16)):
+        s = ipr.ipr_schedule_default(bulk_dtype=dt)
+        ipr.ipr_solve_batched(A, offs, ns, ps, tol, schedule=s, out=C)   # capture + warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, res = ipr.ipr_solve_batched(A, offs, ns, ps, tol, schedule=s, out=C)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t) / reps
+        st = {}
+        for r in res:
+            k = ipr.binding.STATUS_NAMES[r.status]
+            st[k] = st.get(k, 0) + 1
+        its = [r.iters_bulk + r.iters_fp64 for r in res]
+        # products actually run: (p + 1) per iteration, p for the start's M_0
+        # (free for the identity) and p for the final check
+        prods = sum((p + 1) * (r.iters_bulk + r.iters_fp64) + p for p, r in zip(ps, res))
+        fl = sum(((p + 1) * (r.iters_bulk + r.iters_fp64) + p) * 2.0 * n ** 3
+                 for n, p, r in zip(ns, ps, res))
+        out[name] = {"seconds_per_batch": dt_s, "matrices_per_s": len(ns) / dt_s,
+                     "status_counts": st, "mean_iterations": float(np.mean(its)),
+                     "products": prods, "tflops_full_product_equivalent": fl / dt_s / 1e12}
+        log(f"batched {name}", json.dumps(out[name]))
+    return out
 
 
 def main():
@@ -205,7 +299,7 @@ def main():
 
     comps = {}
     if not args.no_comparators:
-        def run(name, **kw):
+        def run(name, _dtype_name=None, **kw):
             s = ipr.ipr_schedule_default(timing=1, **kw)
             need = ipr.ipr_workspace_size(n, p, 1, s)
             wsx = ws if need <= ws.numel() else torch.empty(need, dtype=torch.uint8, device=dev)
@@ -214,10 +308,7 @@ def main():
             _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, workspace=wsx, stream=stream)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
-            d = {"seconds": dt, "status": ipr.binding.STATUS_NAMES[r.status],
-                 "iters_bulk": r.iters_bulk, "iters_fp64": r.iters_fp64, "gemms": r.gemms,
-                 "residual_true": r.residual_true,
-                 "fp64_tflops": (r.gemm_flops / (r.ms_gemm * 1e-3) / 1e12) if r.ms_gemm else None}
+            d = solve_record(ipr, r, dt, _dtype_name)
             log(name, json.dumps(d))
             comps[name] = d
             return d
@@ -247,7 +338,7 @@ def main():
         out["speedup_vs_fp64_full_products"] = fi["seconds"] / sec
         for name, dt in (("fp16", ipr.IPR_FP16), ("fp8_e4m3", ipr.IPR_FP8_E4M3),
                          ("bf16", ipr.IPR_BF16)):
-            run(f"mixed_{name}_bulk_then_fp64", bulk_dtype=dt)
+            run(f"mixed_{name}_bulk_then_fp64", bulk_dtype=dt, _dtype_name=name)
         from paper_1703_02283_amd import train_start
         theta = train_start.load_weights()
         if theta is not None:
@@ -255,6 +346,10 @@ def main():
                     mlp_params=torch.tensor(theta, device=dev))
             out["speedup_learned_vs_identity"] = sec / d["seconds"]
     out["comparators"] = comps
+
+    if not args.no_extra:
+        out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
+        out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
 
     if not args.no_cpu:
         try:

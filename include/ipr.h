@@ -98,6 +98,9 @@ typedef struct {
   int gemm_launches;   /* products timed (schedule.timing = 1) */
   double ms_gemm;      /* their summed device time */
   double gemm_flops;   /* their algorithmic flops: 2 n^3 per full product, n^2 (n + 1) per triangle */
+  int lp_gemm_launches;  /* the same for the low-precision products of the bulk phase */
+  double ms_lp_gemm;     /* (matrix-core kernel only; the rounding of operands is not included) */
+  double lp_gemm_flops;
 } ipr_result;
 
 #define IPR_MLP_NIN 16

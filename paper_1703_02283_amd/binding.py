@@ -36,7 +36,8 @@ class IprResult(ct.Structure):
                 ("ms_norms", ct.c_double),
                 ("ms_init", ct.c_double), ("ms_bulk", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_verify", ct.c_double), ("gemm_launches", ct.c_int), ("ms_gemm", ct.c_double),
-                ("gemm_flops", ct.c_double)]
+                ("gemm_flops", ct.c_double), ("lp_gemm_launches", ct.c_int),
+                ("ms_lp_gemm", ct.c_double), ("lp_gemm_flops", ct.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -167,6 +167,7 @@ struct Prod {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs of timed products
   std::vector<double> flops;
+  std::vector<char> is_lp;     // per timed product: low-precision kernel
   const double* src[NLP] = {};
   bool valid[NLP] = {};
   unsigned long use[NLP] = {};
@@ -209,21 +210,25 @@ struct Prod {
     hipError_t err = hipSuccess;
     ++gemms;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timing && !lowp_dtype) {
+    auto start = [&]() -> hipError_t {
+      if (!timing) return hipSuccess;
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return hipErrorOutOfMemory;
       ev.push_back(e0);
       ev.push_back(e1);
       flops.push_back(tri ? (double)n * n * (n + 1.0) : 2.0 * n * n * (double)n);
-      (void)hipEventRecord(e0, st);
-    }
+      is_lp.push_back(lowp_dtype != 0);
+      return hipEventRecord(e0, st);
+    };
     if (!lowp_dtype) {
+      if ((err = start()) != hipSuccess) return err;
       err = gemm_f64(L, R, n, tri, e, st);
     } else {
       const int a = slot_for(L, -1, &err);
       if (err != hipSuccess) return err;
       const int b = slot_for(R, a, &err);
       if (err != hipSuccess) return err;
+      if ((err = start()) != hipSuccess) return err;
       err = gemm_lp(w->lq[a], w->le[a], w->lq[b], w->le[b], n, lowp_dtype, tri, e, st);
     }
     if (e1) (void)hipEventRecord(e1, st);
@@ -233,14 +238,15 @@ struct Prod {
   }
   int slots(int tri) const { return gemm_partial_slots(n, tri); }
   // after the stream has drained
-  void totals(int* count, double* ms, double* fl) const {
-    *count = (int)flops.size();
-    *ms = 0.0;
-    *fl = 0.0;
+  void totals(int lp, int* count, double* ms, double* fl) const {
+    *count = 0;
+    *ms = *fl = 0.0;
     for (size_t i = 0; i < flops.size(); ++i) {
+      if ((is_lp[i] != 0) != (lp != 0)) continue;
       float t = 0.f;
       if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) *ms += t;
       *fl += flops[i];
+      ++*count;
     }
   }
 };
@@ -354,21 +360,22 @@ struct Solver {
     return IPR_OK;
   }
 
-  // ||I - C^p A||_F from p full products into *tau (host).
+  // ||I - C^p A||_F into *tau (host): the symmetric powers C^2 .. C^p as
+  // triangle products (when enabled), then one full product C^p A.
   int true_residual(double* tau) {
-    const double* src = A;
-    for (int j = 1; j <= p; ++j) {
+    const double* P = C();
+    for (int j = 2; j <= p; ++j) {
       Epilogue e;
-      if (j == p) {
-        e.alpha = -1.0;
-        e.gamma = 1.0;
-        e.partial = w.partial;
-      } else {
-        e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
-      }
-      TRY(prod.f64(C(), src, 0, e));
-      src = e.D;
+      e.D = X[j & 1];  // X[0] for C^2, X[1] (p >= 3) for C^3, ...
+      TRY(prod.f64(C(), P, tri, e));
+      if (!tri) TRY(symmetrize(e.D, n, st));
+      P = e.D;
     }
+    Epilogue e;
+    e.alpha = -1.0;
+    e.gamma = 1.0;
+    e.partial = w.partial;
+    TRY(prod.f64(P, A, 0, e));
     TRY(reduce_fro(w.partial, gemm_partial_slots(n, 0), w.scal + 9, st));
     return read_scalars(w.scal + 9, 1, tau, st);
   }
@@ -607,6 +614,14 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   int status = IPR_EMAXITER;
   int k = 0, kb = 0;
   double rho = 0.0;
+  auto restart_identity = [&]() -> int {
+    res.fallback_used = 1;
+    sv.ci = sv.mi = sv.ni = 0;
+    HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(),
+                          sv.M(), sv.Nb[sv.ni], w.partial, stream));
+    sv.slots = n;
+    return sv.reduce();
+  };
   if (lowp) {
     sv.prod.lowp_dtype = s.bulk_dtype;
     if (p == 1)  // Newton-Schulz bulk: R_0 = I - A C_0
@@ -631,41 +646,33 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     res.iters_bulk = kb;
     if (!std::isfinite(rho) || rho > 1e6) {
       // the low-precision phase diverged: start again in FP64 from the scaled identity
-      res.fallback_used = 1;
       lp_restart = true;
-      sv.ci = sv.mi = sv.ni = 0;
-      HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(),
-                            sv.M(), sv.Nb[sv.ni], w.partial, stream));
-      sv.slots = n;
-      if (int rc = sv.reduce()) return rc;
+      if (int rc = restart_identity()) return rc;
     } else {
       if (int rc = sv.recompute(p == 1)) return rc;
     }
   }
   tm.mark(3);
   // Newton-Schulz order for p = 1 once a low-precision phase has run
-  const bool ns = lowp && p == 1 && !lp_restart;
+  bool ns = lowp && p == 1 && !lp_restart;
   double best = std::numeric_limits<double>::infinity();
   int stale = 0, failed_verify = 0, verified_at = -1;
   double last_tau = std::numeric_limits<double>::infinity();
+  double prev = std::numeric_limits<double>::infinity();
   const int kmax = s.max_iter - res.iters_bulk;
   for (k = 0;; ++k) {
     if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
     res.residual_proxy = rho;
-    if (!std::isfinite(rho) || rho > 1e6) {
-      status = IPR_EDIVERGED;
-      break;
-    }
-    if (rho < tol) {
-      if (ns) {  // R_k = I - A C_k is the true residual
-        res.residual_true = rho;
-        status = IPR_OK;
-        break;
-      }
-      if (!s.verify) {
-        status = IPR_OK;
-        break;
-      }
+    const bool bad = !std::isfinite(rho) || rho > 1e6;
+    // From a start that commutes with A the residual of the coupled form falls
+    // every step until the rounding floor. After a low-precision phase the
+    // iterate carries rounding errors that do not commute with A; for p >= 2
+    // the FP64 steps amplify them, and a growing residual is the sign. Then
+    // (once) start again in FP64 from the scaled identity.
+    const bool rising = rho > 1.1 * prev && rho > 1e-6;
+    prev = rho;
+    bool floor = false;  // stagnation above tol (see below)
+    if (!bad && rho < tol && !ns && s.verify) {
       double tau;
       if (int rc = sv.true_residual(&tau)) return rc;
       res.residual_true = tau;
@@ -674,20 +681,39 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
         status = IPR_OK;
         break;
       }
-      if (++failed_verify >= 2 && !(tau < 0.5 * last_tau)) {
-        status = IPR_EFLOOR;
-        break;
-      }
+      floor = ++failed_verify >= 2 && !(tau < 0.5 * last_tau);
       last_tau = tau;
     }
-    if (rho < 1.0) {
+    if (!bad && rho < 1.0) {
       if (rho < s.stall_ratio * best) {
         best = rho;
         stale = 0;
       } else if (++stale >= 3) {
-        status = IPR_EFLOOR;
-        break;
+        floor = true;
       }
+    }
+    if (lowp && !lp_restart && (bad || rising || floor)) {
+      lp_restart = true;
+      ns = false;
+      if (int rc = restart_identity()) return rc;
+      best = last_tau = prev = std::numeric_limits<double>::infinity();
+      stale = failed_verify = 0;
+      verified_at = -1;
+      --k;  // no step was taken
+      continue;
+    }
+    if (bad) {
+      status = IPR_EDIVERGED;
+      break;
+    }
+    if (rho < tol && (ns || !s.verify)) {
+      if (ns) res.residual_true = rho;  // R_k = I - A C_k is the true residual
+      status = IPR_OK;
+      break;
+    }
+    if (floor) {
+      status = IPR_EFLOOR;
+      break;
     }
     if (k >= kmax) break;
     if (int rc = sv.step(ns)) return rc;
@@ -711,7 +737,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   res.ms_verify = tm.ms(4, 5);
   res.status = status;
   res.gemms = sv.prod.gemms;
-  sv.prod.totals(&res.gemm_launches, &res.ms_gemm, &res.gemm_flops);
+  sv.prod.totals(0, &res.gemm_launches, &res.ms_gemm, &res.gemm_flops);
+  sv.prod.totals(1, &res.lp_gemm_launches, &res.ms_lp_gemm, &res.lp_gemm_flops);
   if (out) *out = res;
   return status;
 }

@@ -294,16 +294,28 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--data", default=None,
+                    help="npz of built data sets: loaded when it exists, else written")
     args = ap.parse_args()
     ipr.load()
     device = torch.device("cuda:0")
     t0 = time.time()
     tr_items = recipe(args.train, 10**6)
     ho_items = recipe(args.heldout, 2 * 10**6)
-    log("building training set")
-    tr = build_dataset(tr_items, device)
-    log("building held-out set")
-    ho = build_dataset(ho_items, device)
+    if args.data and os.path.exists(args.data):
+        with np.load(args.data, allow_pickle=False) as z:
+            tr = {k[3:]: z[k] for k in z.files if k.startswith("tr_")}
+            ho = {k[3:]: z[k] for k in z.files if k.startswith("ho_")}
+        assert len(tr["feats"]) == len(tr_items) and len(ho["feats"]) == len(ho_items)
+        log(f"loaded data sets from {args.data}")
+    else:
+        log("building training set")
+        tr = build_dataset(tr_items, device)
+        log("building held-out set")
+        ho = build_dataset(ho_items, device)
+        if args.data:
+            np.savez(args.data, **{"tr_" + k: v for k, v in tr.items()},
+                     **{"ho_" + k: v for k, v in ho.items()})
     t1 = time.time()
     theta, final_loss = train(tr, device, epochs=args.epochs)
     t2 = time.time()

@@ -57,3 +57,33 @@ def test_binding_loads_and_host_only_calls_work(lib):
 def test_binding_signatures_match_header(lib):
     from paper_1703_02283_amd import binding
     assert set(binding._SIGS) == set(declared())
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of ipr_schedule / ipr_result have the header's field
+    offsets and sizes (checked with the host compiler, no GPU)."""
+    import ctypes as ct
+    from paper_1703_02283_amd import binding
+    lines = ["#include <cstdio>", "#include <cstddef>", '#include "ipr.h"', "int main() {"]
+    for cname, cls in (("ipr_schedule", binding.IprSchedule), ("ipr_result", binding.IprResult)):
+        lines.append(f'  std::printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  std::printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I",
+                        os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", str(src),
+                        "-o", str(exe)], capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.fail(r.stderr[-2000:])
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                               check=True).stdout.splitlines():
+        a, b, c = line.split()
+        got[(a, b)] = int(c)
+    for cname, cls in (("ipr_schedule", binding.IprSchedule), ("ipr_result", binding.IprResult)):
+        assert got[(cname, "size")] == ct.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
