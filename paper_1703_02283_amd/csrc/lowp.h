@@ -7,7 +7,7 @@ namespace ipr {
 // Same codes as ipr_dtype.
 enum { LP_BF16 = 1, LP_FP16 = 2, LP_FP8 = 3 };
 
-int lp_padded(int n);              // n rounded up to a multiple of 128
+int lp_padded(int n);              // n rounded up to a multiple of 256
 int lp_esize(int dtype);           // bytes per code
 size_t lp_bytes(int n, int dtype); // bytes of one padded code matrix
 size_t lp_exp_count(int n);        // ints of one tile-exponent array

@@ -6,13 +6,12 @@
 //    nearest, ties to even, from the float64 value directly) after scaling each
 //    128 x 128 tile by a power of two that puts its largest magnitude in
 //    [2^top, 2^(top+1)) (none for bf16, whose range is float32's). The codes are
-//    written transposed and zero padded to a multiple of 128, which is the
-//    k-contiguous layout the matrix-core operands want: lane l of a 16x16x32
-//    MFMA supplies 8 consecutive k of one row.
-//  * gemm_lp: D = L^T R from two such operands, fp32 accumulation on
-//    v_mfma_f32_16x16x32_{bf16,f16} or v_mfma_f32_16x16x32_fp8_fp8, with the
-//    per-tile scales applied once per 128-wide k block, then the float64
-//    epilogue shared with the FP64 kernel.
+//    written transposed and zero padded to a multiple of 256, which is the
+//    k-contiguous layout the matrix-core operands want (a lane supplies 8 or 32
+//    consecutive k of one row).
+//  * gemm_lp: D = L^T R from two such operands on the matrix cores with fp32
+//    accumulation, then the float64 epilogue shared with the FP64 kernel
+//    (details at the kernel).
 #include <cstdint>
 
 #include "kernels_common.h"
@@ -26,6 +25,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int TILE = 128;
+constexpr int kZeroTile = -(1 << 20);   // exponent of an all-zero tile
 constexpr int NT = 256;
 
 struct Fmt {
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    int e = 0;
-    if (f.top > -1000 && red[0] > 0.0) e = ilogb(red[0]) - f.top;
-    sh_e = e;
+    // an all-zero tile gets kZeroTile, which the product kernel skips
+    int e = kZeroTile;
+    if (red[0] > 0.0) e = f.top > -1000 ? ilogb(red[0]) - f.top : 0;
+    sh_e = e == kZeroTile ? 0 : e;
     E[tc * ntp + tr] = e;   // transposed tile index, like the codes
   }
   __syncthreads();
@@ -122,150 +123,282 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
   }
 }
 
-// D = L^T R from k-contiguous codes Lt (row i), Rt (row j), order np (multiple of 128).
-// ESZ = bytes per code. 4 waves (2 x 2) x 64 x 64 per wave.
-constexpr int ROWB = 128;        // bytes of k per LDS row and stage
-constexpr int PITCH = ROWB + 16; // LDS row pitch in bytes
+// D = L^T R from k-contiguous codes Lt (row i), Rt (row j), order np (a
+// multiple of 256), on 256 x 256 output tiles.
+//
+// * 4 waves (2 x 2), each a 128 x 128 sub-tile = 4 x 4 blocks of 32 x 32
+//   (v_mfma_f32_32x32x16_{bf16,f16}: lane l supplies row l % 32, k 8 (l / 32)
+//   .. + 7; v_mfma_scale_f32_32x32x64_f8f6f4 for fp8: k 32 (l / 32) .. + 31).
+//   A wave's 128 rows and columns are one 128 x 128 exponent tile each.
+// * k is staged 64 bytes per row at a time through a ring of NSTG LDS buffers
+//   filled by direct global -> LDS loads (16 bytes per lane, the lane's data
+//   lands at base + 16 lane), NSTG - 1 stages ahead of the matrix cores. In
+//   LDS a row is 4 chunks of 16 bytes, chunk c of row r stored at c ^ ((r / 2)
+//   & 3): the fragment reads of 8 consecutive rows then hit distinct banks.
+// * Per-tile exponents: fp8 passes them to the matrix core as block scales
+//   (E8M0 127 + e, exact). fp16 keeps the accumulator in units of 2^Sref,
+//   Sref = max over k-tiles of eL + eR for the wave's exponent tiles, and
+//   multiplies the A fragments of k-tile t by 2^(eL + eR - Sref) <= 1 (exact
+//   unless it underflows fp16, i.e. below 2^-24 of the largest k-tile's scale).
+//   bf16 is unscaled.
+constexpr int BT = 256;                 // output tile edge
+constexpr int KB = 64;                  // bytes of k per row and stage
+constexpr int NSTG = 4;                 // LDS ring depth
+constexpr int STG_BYTES = BT * KB;      // one operand, one stage
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
+
+template <int V>
+struct Ic {
+  static constexpr int value = V;
+};
+
+// A compiler-only fence: keeps LDS reads and writes on their side of a
+// barrier without the hardware wait that __syncthreads adds for every
+// outstanding load (the ring's loads of later stages must stay in flight).
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 
 template <int ESZ, int DT>
-__global__ __launch_bounds__(NT, 2) void gemm_lp_kernel(const uint8_t* __restrict__ Lt,
+__global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restrict__ Lt,
                                                         const uint8_t* __restrict__ Rt,
                                                         const int* __restrict__ EL,
                                                         const int* __restrict__ ER, int n,
                                                         int np, Grid gr, int tri, Epilogue e) {
-  __shared__ __attribute__((aligned(16))) uint8_t As[2][TILE * PITCH];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][TILE * PITCH];
+  // one array per ring slot: distinct objects let the compiler see that the
+  // loads in flight into other slots do not alias the slot being read
+  __shared__ __attribute__((aligned(16))) uint8_t A0[STG_BYTES], A1[STG_BYTES], A2[STG_BYTES],
+      A3[STG_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t B0[STG_BYTES], B1[STG_BYTES], B2[STG_BYTES],
+      B3[STG_BYTES];
   __shared__ double red[NT / 64];
-  constexpr int BKE = ROWB / ESZ;             // k elements per stage
-  constexpr int KSTEPS = BKE / 32;            // MFMA k steps (32 each) per stage
-  constexpr int STAGES_PER_SCALE = TILE / BKE;
-  constexpr bool SCALED = DT != LP_BF16;
+  __shared__ double post_sh[4];             // per wave: fp16 result scale 2^Sref
+  constexpr int KEL = KB / ESZ;             // k elements per stage
+  constexpr int ST_PER_KT = TILE / KEL;     // stages per 128-wide exponent tile
+  static_assert(NSTG == 4, "four ring slots");
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lw = logical_wg();
   int bi, bj;
   if (!tile_of(lw, gr, tri, &bi, &bj)) {
     if (e.partial && tid == 0) e.partial[lw] = 0.0;
     return;
   }
-  const int i0 = bi * TILE, j0 = bj * TILE;
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int i0 = bi * BT, j0 = bj * BT;
+  const int wm = wave >> 1, wn = wave & 1;
   const int ntp = np / TILE;
+  const int ib = 2 * bi + wm, jb = 2 * bj + wn;   // the wave's exponent tiles
+  const size_t ldb = (size_t)np * ESZ;
 
-  v4f acc[4][4], blk[4][4];
+  // exponent reference (fp16)
+  int sref = 0;
+  if constexpr (DT == LP_FP16) {
+    sref = kZeroTile;   // stays so only when every product of tiles is zero
+    for (int kt = 0; kt < ntp; ++kt) {
+      const int el = EL[ib * ntp + kt], er = ER[jb * ntp + kt];
+      if (el == kZeroTile || er == kZeroTile) continue;
+      sref = el + er > sref ? el + er : sref;
+    }
+  }
+
+  // loader: instruction q of wave w fills rows 64 w + 16 q .. + 15 of a stage;
+  // lane l's 16 bytes land at row (l / 4), physical chunk l % 4
+  const int lrow = lane >> 2;
+  const uint8_t* gA[4];
+  const uint8_t* gB[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = 64 * wave + 16 * q + lrow;
+    const int c = swz(row, lane & 3);
+    gA[q] = Lt + (size_t)(i0 + row) * ldb + 16 * c;
+    gB[q] = Rt + (size_t)(j0 + row) * ldb + 16 * c;
+  }
+  auto issue = [&](auto S, int st) {
+    constexpr int sl = decltype(S)::value;
+    uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
+    uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
+    const size_t kb0 = (size_t)st * KB;
+    // LDS destinations as plain addresses (wave-uniform, in scalar registers)
+    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)as);
+    const uint32_t lb = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)bs);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t off = (64 * wave + 16 * q) * KB;
+      __builtin_amdgcn_global_load_lds((const void*)(gA[q] + kb0), (lds_void*)(uintptr_t)(la + off),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(gB[q] + kb0), (lds_void*)(uintptr_t)(lb + off),
+                                       16, 0, 0);
+    }
+  };
+
+  v16f acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-      blk[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-    }
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  // loader: 128 rows x 128 bytes per operand = 1024 chunks of 16 B; thread t
-  // moves rows (t / 8) + 32 q, bytes 16 (t % 8).
-  const int lrow = tid >> 3, lcb = (tid & 7) * 16;
-  uint4 ga[4], gb[4];
-  auto gload = [&](int kb) {  // kb = first k byte
+  const int frow = lane & 31, fhalf = lane >> 5;
+  auto compute = [&](auto S, int st) {
+    constexpr int sl = decltype(S)::value;
+    const uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
+    const uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
+    const int kt = st / ST_PER_KT;
+    if constexpr (ESZ == 2) {
+      _Float16 fsc = (_Float16)1.0f;
+      bool scale_a = false;
+      if constexpr (DT == LP_FP16) {
+        const int el = EL[ib * ntp + kt], er = ER[jb * ntp + kt];
+        // (a zero tile's codes are zero: any scale will do)
+        const int d = (el == kZeroTile || er == kZeroTile) ? 0 : el + er - sref;
+        scale_a = d != 0;
+        fsc = (_Float16)ldexpf(1.0f, d < -30 ? -30 : d);
+      }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = lrow + 32 * q;
-      ga[q] = *reinterpret_cast<const uint4*>(Lt + (size_t)(i0 + r) * np * ESZ + kb + lcb);
-      gb[q] = *reinterpret_cast<const uint4*>(Rt + (size_t)(j0 + r) * np * ESZ + kb + lcb);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = lrow + 32 * q;
-      *reinterpret_cast<uint4*>(&As[buf][r * PITCH + lcb]) = ga[q];
-      *reinterpret_cast<uint4*>(&Bs[buf][r * PITCH + lcb]) = gb[q];
-    }
-  };
-
-  const int nstage = np * ESZ / ROWB;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  const int fr = lane >> 4, fc = lane & 15;
-  for (int st = 0; st < nstage; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nstage) gload((st + 1) * ROWB);
-#pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-      const int kbyte = (ks * 32 + fr * 8) * ESZ;
-      if constexpr (ESZ == 2) {
-        v8bf abf[4], bbf[4];
-        v8h ah[4], bh[4];
+      for (int ks = 0; ks < KB / 32; ++ks) {
+        const int c = 2 * ks + fhalf;
+        uint4 av[4], bv[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          uint4 v = *reinterpret_cast<const uint4*>(&As[buf][(wm0 + a * 16 + fc) * PITCH + kbyte]);
-          if constexpr (DT == LP_BF16) abf[a] = __builtin_bit_cast(v8bf, v);
-          else ah[a] = __builtin_bit_cast(v8h, v);
+          const int row = wm * 128 + a * 32 + frow;
+          av[a] = *reinterpret_cast<const uint4*>(as + row * KB + 16 * swz(row, c));
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          uint4 v = *reinterpret_cast<const uint4*>(&Bs[buf][(wn0 + b * 16 + fc) * PITCH + kbyte]);
-          if constexpr (DT == LP_BF16) bbf[b] = __builtin_bit_cast(v8bf, v);
-          else bh[b] = __builtin_bit_cast(v8h, v);
+          const int row = wn * 128 + b * 32 + frow;
+          bv[b] = *reinterpret_cast<const uint4*>(bs + row * KB + 16 * swz(row, c));
+        }
+        if constexpr (DT == LP_FP16) {
+          if (scale_a) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              v8h h = __builtin_bit_cast(v8h, av[a]);
+              h = h * fsc;
+              av[a] = __builtin_bit_cast(uint4, h);
+            }
+          }
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             if constexpr (DT == LP_BF16)
-              blk[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(abf[a], bbf[b], blk[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(v8bf, av[a]), __builtin_bit_cast(v8bf, bv[b]), acc[a][b], 0, 0,
+                  0);
             else
-              blk[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], blk[a][b], 0, 0, 0);
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(v8h, av[a]), __builtin_bit_cast(v8h, bv[b]), acc[a][b], 0, 0,
+                  0);
           }
-      } else {
-        long a8[4], b8[4];
+      }
+    } else {
+      // fp8: one 64-k step per stage, 32 bytes (two chunks) per lane
+      // E8M0 block scales; tiles beyond float32's range clamp (they cannot
+      // be accumulated in float32 anyway)
+      const int sa = min(254, max(1, 127 + EL[ib * ntp + kt]));
+      const int sb = min(254, max(1, 127 + ER[jb * ntp + kt]));
+      v8i av[4], bv[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-          a8[a] = *reinterpret_cast<const long*>(&As[buf][(wm0 + a * 16 + fc) * PITCH + kbyte]);
+      for (int a = 0; a < 4; ++a) {
+        const int row = wm * 128 + a * 32 + frow;
+        const uint4 lo = *reinterpret_cast<const uint4*>(as + row * KB + 16 * swz(row, 2 * fhalf));
+        const uint4 hi =
+            *reinterpret_cast<const uint4*>(as + row * KB + 16 * swz(row, 2 * fhalf + 1));
+        av[a] = (v8i){(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = wn * 128 + b * 32 + frow;
+        const uint4 lo = *reinterpret_cast<const uint4*>(bs + row * KB + 16 * swz(row, 2 * fhalf));
+        const uint4 hi =
+            *reinterpret_cast<const uint4*>(bs + row * KB + 16 * swz(row, 2 * fhalf + 1));
+        bv[b] = (v8i){(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          b8[b] = *reinterpret_cast<const long*>(&Bs[buf][(wn0 + b * 16 + fc) * PITCH + kbyte]);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            blk[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8[a], b8[b], blk[a][b], 0, 0, 0);
-      }
+          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[a], bv[b], acc[a][b], 0,
+                                                                      0, 0, sa, 0, sb);
     }
-    if constexpr (SCALED) {
-      if ((st + 1) % STAGES_PER_SCALE == 0) {
-        const int kt = st / STAGES_PER_SCALE;
-        const float sc = ldexpf(1.0f, EL[bi * ntp + kt] + ER[bj * ntp + kt]);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            acc[a][b] += sc * blk[a][b];
-            blk[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-          }
-      }
-    }
-    if (st + 1 < nstage) lstore(buf ^ 1);
-    __syncthreads();
+  };
+
+  // (s_waitcnt fields: vmcnt bits 3:0 and 15:14, expcnt 6:4 = 7, lgkmcnt
+  // 11:8 = 15, i.e. only the vector-memory count is waited on; a stage is 8
+  // loads per lane)
+  auto stage = [&](auto S, int st, int nst) {
+    constexpr int sl = decltype(S)::value;
+    const int after = nst - 1 - st;   // stages issued after st (at most 2)
+    if (after >= 2) __builtin_amdgcn_s_waitcnt(0x4F70);       // vmcnt(16)
+    else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+    wg_barrier();  // stage st is in LDS for every wave; slot (st + 3) % 4 is free
+    if (st + 3 < nst) issue(Ic<(sl + 3) % 4>{}, st + 3);
+    compute(S, st);
+  };
+
+  const int nst = (int)(ldb / KB);  // a multiple of 4 (np is a multiple of 256)
+  issue(Ic<0>{}, 0);
+  issue(Ic<1>{}, 1);
+  issue(Ic<2>{}, 2);
+  for (int st = 0; st < nst; st += 4) {
+    stage(Ic<0>{}, st, nst);
+    stage(Ic<1>{}, st + 1, nst);
+    stage(Ic<2>{}, st + 2, nst);
+    stage(Ic<3>{}, st + 3, nst);
   }
-  // f32 16x16 output layout: row 4 (lane / 16) + r, column lane % 16
+
+  // Epilogue through LDS, one 32-row block of each wave at a time: the waves
+  // write their fp32 results row-major into a 64 x 256 staging area (the ring
+  // slots), then thread t takes column t of the 64 rows.
+  // 32 x 32 f32 output layout: register r of lane l is row (r % 4) + 8 (r / 4)
+  // + 4 (l / 32), column l % 32.
+  // the staging area holds each wave's results in its own units (fp16: 2^Sref)
+  if (lane == 0)
+    post_sh[wave] = DT != LP_FP16 ? 1.0 : sref == kZeroTile ? 0.0 : ldexp(1.0, sref);
   double psum = 0.0;
+  auto stg_at = [&](int row, int col) -> float* {
+    // rows 0..15 in A0, 16..31 in A1, 32..47 in A2, 48..63 in A3 (16 KB each)
+    float* base = reinterpret_cast<float*>(row < 16 ? A0 : row < 32 ? A1 : row < 48 ? A2 : A3);
+    return base + (row & 15) * 256 + col;
+  };
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int h = 0; h < 4; ++h) {
+    wg_barrier();  // previous users of the staging area are done
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float v = SCALED ? acc[a][b][r] : blk[a][b][r];
-        epilogue_element(e, n, tri, i0 + wm0 + a * 16 + 4 * fr + r, j0 + wn0 + b * 16 + fc,
-                         (double)v, psum);
+      for (int r = 0; r < 16; ++r) {
+        const int row = wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * fhalf;
+        const int col = wn * 128 + b * 32 + frow;
+        *stg_at(row, col) = acc[h][b][r];
       }
+    wg_barrier();
+    for (int q = 0; q < 64; ++q) {
+      const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
+      const int j = j0 + tid;
+      const double post = post_sh[(q >> 5) * 2 + (tid >> 7)];  // the owning wave's
+      epilogue_element(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
+    }
+  }
   if (e.partial) store_partial(e.partial, lw, psum, red);
 }
 
 }  // namespace
 
-int lp_padded(int n) { return (n + TILE - 1) / TILE * TILE; }
+int lp_padded(int n) { return (n + BT - 1) / BT * BT; }
 int lp_esize(int dtype) { return dtype == LP_FP8 ? 1 : 2; }
 size_t lp_bytes(int n, int dtype) {
   const size_t np = lp_padded(n);
@@ -275,7 +408,7 @@ size_t lp_exp_count(int n) {
   const size_t t = lp_padded(n) / TILE;
   return t * t;
 }
-int lp_partial_slots(int n, int tri) { return make_grid(n, tri, TILE).nwg; }
+int lp_partial_slots(int n, int tri) { return make_grid(n, tri, BT).nwg; }
 
 hipError_t quantize_t(const double* X, int n, int dtype, void* Q, int* E, hipStream_t stream) {
   const int np = lp_padded(n), ntp = np / TILE;
@@ -294,7 +427,7 @@ hipError_t gemm_lp(const void* Lq, const int* EL, const void* Rq, const int* ER,
   if (!Lq || !Rq || !EL || !ER) return hipErrorInvalidValue;
   const int np = lp_padded(n);
   // tiles beyond n are empty: grid over the unpadded order
-  Grid gr = make_grid(n, tri, TILE);
+  Grid gr = make_grid(n, tri, BT);
   const uint8_t* L = (const uint8_t*)Lq;
   const uint8_t* R = (const uint8_t*)Rq;
   switch (dtype) {

@@ -236,7 +236,10 @@ struct Prod {
     if (e.S) invalidate(e.S);
     return err;
   }
-  int slots(int tri) const { return gemm_partial_slots(n, tri); }
+  // partial sums written by the last product (the kernels' grids differ)
+  int slots(int tri) const {
+    return lowp_dtype ? lp_partial_slots(n, tri) : gemm_partial_slots(n, tri);
+  }
   // after the stream has drained
   void totals(int lp, int* count, double* ms, double* fl) const {
     *count = 0;
