@@ -81,6 +81,7 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
                                                          int* __restrict__ E) {
   __shared__ double red[NT];
   __shared__ int sh_e;
+  __shared__ __attribute__((aligned(16))) T cT[TILE][TILE + 2];   // codes, transposed
   const int tr = blockIdx.y, tc = blockIdx.x;
   const int r0 = tr * TILE, c0 = tc * TILE;
   const Fmt f = fmt_of(dtype);
@@ -105,21 +106,39 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
   }
   __syncthreads();
   const double scale = ldexp(1.0, -sh_e);
-  // transposed write: output row c (input column), 128 consecutive r.
-  // thread t handles output row c0 + t/2, r in [r0 + 64 (t%2), +64)
-  const int c = c0 + (threadIdx.x >> 1);
-  const int rb = r0 + 64 * (threadIdx.x & 1);
-  T* qrow = Q + (size_t)c * ldq;
-  for (int rr = 0; rr < 64; ++rr) {
-    const int r = rb + rr;
-    double v = (r < n && c < n) ? X[(size_t)r * n + c] * scale : 0.0;
+  // codes in input order (coalesced reads of X; the tile is L2-resident from
+  // the pass above) into LDS, transposed: cT[c][r]
+  for (int t = threadIdx.x; t < TILE * TILE; t += NT) {
+    const int rl = t / TILE, cl = t % TILE;
+    const int r = r0 + rl, c = c0 + cl;
+    const double v = (r < n && c < n) ? X[(size_t)r * n + c] * scale : 0.0;
     const double y = round_fmt(v, f);
     T code;
     if constexpr (sizeof(T) == 2)
       code = dtype == LP_BF16 ? bits_bf16(y) : bits_fp16(y);
     else
       code = bits_e4m3(y);
-    qrow[r] = code;
+    cT[cl][rl] = code;
+  }
+  __syncthreads();
+  // rows of Q (= columns of X) in 16-byte pieces: consecutive threads write
+  // consecutive pieces of a row
+  constexpr int PER = 16 / sizeof(T);          // codes per piece
+  constexpr int PIECES = TILE / PER;           // pieces per row
+  for (int t = threadIdx.x; t < TILE * PIECES; t += NT) {
+    const int cl = t / PIECES, pc = t % PIECES;
+    const T* src = &cT[cl][pc * PER];
+    uint32_t wd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (sizeof(T) == 2)
+        wd[k] = (uint32_t)src[2 * k] | ((uint32_t)src[2 * k + 1] << 16);
+      else
+        wd[k] = (uint32_t)src[4 * k] | ((uint32_t)src[4 * k + 1] << 8) |
+                ((uint32_t)src[4 * k + 2] << 16) | ((uint32_t)src[4 * k + 3] << 24);
+    }
+    *reinterpret_cast<uint4*>(Q + (size_t)(c0 + cl) * ldq + r0 + pc * PER) =
+        make_uint4(wd[0], wd[1], wd[2], wd[3]);
   }
 }
 
@@ -150,7 +169,12 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 1) & 3); }
+// Physical chunk of logical 16-byte chunk `chunk` in LDS row `row`. Any 8
+// consecutive rows read at one logical chunk cover a 128-byte period, and
+// any 16 a 256-byte period, without two lanes on one bank.
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return chunk ^ ((row >> 1) & 3) ^ (((row >> 3) & 1) * 3);
+}
 
 template <int V>
 struct Ic {
@@ -263,10 +287,10 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
         scale_a = d != 0;
         fsc = (_Float16)ldexpf(1.0f, d < -30 ? -30 : d);
       }
-#pragma unroll
-      for (int ks = 0; ks < KB / 32; ++ks) {
+      // fragments of k-step ks + 1 are read while the matrix cores work on
+      // k-step ks (two MFMAs per LDS read)
+      auto load = [&](int ks, uint4* av, uint4* bv) {
         const int c = 2 * ks + fhalf;
-        uint4 av[4], bv[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           const int row = wm * 128 + a * 32 + frow;
@@ -277,13 +301,21 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
           const int row = wn * 128 + b * 32 + frow;
           bv[b] = *reinterpret_cast<const uint4*>(bs + row * KB + 16 * swz(row, c));
         }
+      };
+      uint4 av[2][4], bv[2][4];
+      load(0, av[0], bv[0]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < KB / 32; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < KB / 32) load(ks + 1, av[cur ^ 1], bv[cur ^ 1]);
         if constexpr (DT == LP_FP16) {
           if (scale_a) {
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-              v8h h = __builtin_bit_cast(v8h, av[a]);
+              v8h h = __builtin_bit_cast(v8h, av[cur][a]);
               h = h * fsc;
-              av[a] = __builtin_bit_cast(uint4, h);
+              av[cur][a] = __builtin_bit_cast(uint4, h);
             }
           }
         }
@@ -293,13 +325,23 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
           for (int b = 0; b < 4; ++b) {
             if constexpr (DT == LP_BF16)
               acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  __builtin_bit_cast(v8bf, av[a]), __builtin_bit_cast(v8bf, bv[b]), acc[a][b], 0, 0,
-                  0);
+                  __builtin_bit_cast(v8bf, av[cur][a]), __builtin_bit_cast(v8bf, bv[cur][b]),
+                  acc[a][b], 0, 0, 0);
             else
               acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                  __builtin_bit_cast(v8h, av[a]), __builtin_bit_cast(v8h, bv[b]), acc[a][b], 0, 0,
-                  0);
+                  __builtin_bit_cast(v8h, av[cur][a]), __builtin_bit_cast(v8h, bv[cur][b]),
+                  acc[a][b], 0, 0, 0);
           }
+        if constexpr (DT == LP_BF16) {
+          if (ks + 1 < KB / 32) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 DS read
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       // fp8: one 64-k step per stage, 32 bytes (two chunks) per lane
