@@ -122,18 +122,37 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * BK);
+    // operands of k-step kk + 4 are read from LDS while the matrix cores
+    // work on k-step kk (an LDS read between pairs of MFMAs), so the two
+    // waves of a SIMD do not both wait on LDS at the start of a step
+    double av[2][FM], bv[2][FN];
+    auto fload = [&](int kk, double* a_, double* b_) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a) a_[a] = Ls[buf][kk + fr][wm0 + a * 16 + fc];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) b_[b] = Rs[buf][kk + fr][wn0 + b * 16 + fc];
+    };
+    fload(0, av[0], bv[0]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double av[FM], bv[FN];
-#pragma unroll
-      for (int a = 0; a < FM; ++a) av[a] = Ls[buf][kk + fr][wm0 + a * 16 + fc];
-#pragma unroll
-      for (int b = 0; b < FN; ++b) bv[b] = Rs[buf][kk + fr][wn0 + b * 16 + fc];
+      const int cur = (kk >> 2) & 1;
+      if (kk + 4 < BK) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b)
-          slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], slab[a][b], 0, 0, 0);
+          slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], slab[a][b],
+                                                            0, 0, 0);
+      if (kk + 4 < BK) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (kt % FLUSH == FLUSH - 1 || kt + 1 == nk) {
 #pragma unroll

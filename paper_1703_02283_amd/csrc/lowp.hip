@@ -12,6 +12,7 @@
 //  * gemm_lp: D = L^T R from two such operands on the matrix cores with fp32
 //    accumulation, then the float64 epilogue shared with the FP64 kernel
 //    (details at the kernel).
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels_common.h"
@@ -210,12 +211,20 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lw = logical_wg();
+  // Persistent: one workgroup per CU; the workgroups of an XCD (w % 8) walk
+  // that XCD's run of logical tiles together, 32 consecutive tiles at a time,
+  // so their row and column panels are read from its L2 at about the same k.
+  const int per = gr.nwg >> 3;            // logical tiles per XCD
+  const int nx = gridDim.x >> 3;          // workgroups per XCD
+  const int xcd = blockIdx.x & 7;
+  for (int t = blockIdx.x >> 3; t < per; t += nx) {
+  const int lw = xcd * per + t;
   int bi, bj;
   if (!tile_of(lw, gr, tri, &bi, &bj)) {
     if (e.partial && tid == 0) e.partial[lw] = 0.0;
-    return;
+    continue;
   }
+  wg_barrier();  // the previous tile's epilogue is done with the LDS
   const int i0 = bi * BT, j0 = bj * BT;
   const int wm = wave >> 1, wn = wave & 1;
   const int ntp = np / TILE;
@@ -436,6 +445,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
     }
   }
   if (e.partial) store_partial(e.partial, lw, psum, red);
+  }
 }
 
 }  // namespace
@@ -472,17 +482,25 @@ hipError_t gemm_lp(const void* Lq, const int* EL, const void* Rq, const int* ER,
   Grid gr = make_grid(n, tri, BT);
   const uint8_t* L = (const uint8_t*)Lq;
   const uint8_t* R = (const uint8_t*)Rq;
+  static thread_local int ncu = 0;
+  if (!ncu) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+  }
+  const int grid = std::max(8, std::min(gr.nwg, ncu / 8 * 8));
   switch (dtype) {
     case LP_BF16:
-      hipLaunchKernelGGL((gemm_lp_kernel<2, LP_BF16>), dim3(gr.nwg), dim3(NT), 0, stream, L, R,
+      hipLaunchKernelGGL((gemm_lp_kernel<2, LP_BF16>), dim3(grid), dim3(NT), 0, stream, L, R,
                          EL, ER, n, np, gr, tri, e);
       break;
     case LP_FP16:
-      hipLaunchKernelGGL((gemm_lp_kernel<2, LP_FP16>), dim3(gr.nwg), dim3(NT), 0, stream, L, R,
+      hipLaunchKernelGGL((gemm_lp_kernel<2, LP_FP16>), dim3(grid), dim3(NT), 0, stream, L, R,
                          EL, ER, n, np, gr, tri, e);
       break;
     default:
-      hipLaunchKernelGGL((gemm_lp_kernel<1, LP_FP8>), dim3(gr.nwg), dim3(NT), 0, stream, L, R,
+      hipLaunchKernelGGL((gemm_lp_kernel<1, LP_FP8>), dim3(grid), dim3(NT), 0, stream, L, R,
                          EL, ER, n, np, gr, tri, e);
   }
   return hipGetLastError();
