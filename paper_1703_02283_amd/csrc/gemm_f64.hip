@@ -46,6 +46,21 @@ constexpr int LDP = BM + 16;   // LDS row pitch in doubles
 constexpr int NT = 512;        // threads per workgroup (8 waves)
 constexpr int FLUSH = 2;       // slabs (2 x 32 = 64 k) per slab accumulator
 constexpr int NQ = BK / 8;     // loader passes (8 rows of 128 per pass)
+// interior tiles: k slabs of 16 rows in a ring of 4 LDS slots (the same LDS
+// as the two 32-row buffers of the edge path), filled by direct loads
+constexpr int BKD = 16;
+constexpr int NSLOT = 4;
+constexpr int FLUSHD = 4;      // 4 x 16 = 64 k per slab accumulator
+static_assert(NSLOT * BKD == 2 * BK, "the two paths share the LDS buffers");
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// compiler-only fence around a hardware barrier: no wait for loads in flight
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 
 __global__ __launch_bounds__(NT, 1)
 void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R, int n,
@@ -76,95 +91,175 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
       sum[a][b] = slab[a][b];
     }
 
-  // Loader: 32 rows x 128 columns per operand = 2048 double2; thread t moves
-  // rows (t / 64) + 8q, q = 0..3, columns 2 (t % 64) and 2 (t % 64) + 1.
-  const int lrow = tid >> 6;
-  const int lcol = (tid & 63) * 2;
-  const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
-  double2 la[NQ], ra[NQ];
-
-  auto gload = [&](int k0) {
-    if (cols_in && k0 + BK <= n) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const size_t row = (size_t)(k0 + lrow + 8 * q) * n;
-        la[q] = *reinterpret_cast<const double2*>(L + row + i0 + lcol);
-        ra[q] = *reinterpret_cast<const double2*>(R + row + j0 + lcol);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int k = k0 + lrow + 8 * q;
-        const size_t row = (size_t)k * n;
-        const bool kin = k < n;
-        la[q].x = (kin && i0 + lcol < n) ? L[row + i0 + lcol] : 0.0;
-        la[q].y = (kin && i0 + lcol + 1 < n) ? L[row + i0 + lcol + 1] : 0.0;
-        ra[q].x = (kin && j0 + lcol < n) ? R[row + j0 + lcol] : 0.0;
-        ra[q].y = (kin && j0 + lcol + 1 < n) ? R[row + j0 + lcol + 1] : 0.0;
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      *reinterpret_cast<double2*>(&Ls[buf][lrow + 8 * q][lcol]) = la[q];
-      *reinterpret_cast<double2*>(&Rs[buf][lrow + 8 * q][lcol]) = ra[q];
-    }
-  };
-
-  const int nk = (n + BK - 1) / BK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-
   const int fr = lane >> 4;   // k row of this lane's operand element
   const int fc = lane & 15;   // m (or n) index of this lane's operand element
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    // operands of k-step kk + 4 are read from LDS while the matrix cores
-    // work on k-step kk (an LDS read between pairs of MFMAs), so the two
-    // waves of a SIMD do not both wait on LDS at the start of a step
-    double av[2][FM], bv[2][FN];
-    auto fload = [&](int kk, double* a_, double* b_) {
+  const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
+
+  if (cols_in && n % BKD == 0) {
+    // Interior tile: each wave moves k rows 2w and 2w + 1 of L and R per slab
+    // straight into LDS (64 lanes x 16 bytes = one 128-double row), two slabs
+    // ahead of the matrix cores; only the slab about to be read is waited for.
+    double (*Lr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Ls[0][0][0]);
+    double (*Rr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Rs[0][0][0]);
+    auto issue = [&](int sl) {
+      const int slot = sl % NSLOT;
 #pragma unroll
-      for (int a = 0; a < FM; ++a) a_[a] = Ls[buf][kk + fr][wm0 + a * 16 + fc];
-#pragma unroll
-      for (int b = 0; b < FN; ++b) b_[b] = Rs[buf][kk + fr][wn0 + b * 16 + fc];
-    };
-    fload(0, av[0], bv[0]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int cur = (kk >> 2) & 1;
-      if (kk + 4 < BK) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], slab[a][b],
-                                                            0, 0, 0);
-      if (kk + 4 < BK) {
-#pragma unroll
-        for (int g = 0; g < 3; ++g) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
-        }
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      for (int h = 0; h < 2; ++h) {
+        const int row = 2 * wave + h;
+        const size_t g = (size_t)(sl * BKD + row) * n + 2 * lane;
+        // LDS destinations as plain wave-uniform addresses
+        const uint32_t ll = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(lds_void*)&Lr[slot][row][0]);
+        const uint32_t lr = __builtin_amdgcn_readfirstlane(
+            (uint32_t)(uintptr_t)(lds_void*)&Rr[slot][row][0]);
+        __builtin_amdgcn_global_load_lds((const void*)(L + g + i0), (lds_void*)(uintptr_t)ll, 16,
+                                         0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(R + g + j0), (lds_void*)(uintptr_t)lr, 16,
+                                         0, 0);
       }
+    };
+    const int nk = n / BKD;
+    issue(0);
+    if (nk > 1) issue(1);
+    if (nk > 2) issue(2);
+    for (int sl = 0; sl < nk; ++sl) {
+      // (s_waitcnt: vmcnt in bits 3:0, expcnt 6:4 = 7, lgkmcnt 11:8 = 15;
+      // a slab is 4 loads per lane)
+      const int after = nk - 1 - sl;
+      if (after >= 2) __builtin_amdgcn_s_waitcnt(0x0F78);       // vmcnt(8)
+      else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4)
+      else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+      wg_barrier();  // slab sl is in LDS for every wave; slot (sl + 3) % 4 is free
+      if (sl + 3 < nk) issue(sl + 3);
+      const int slot = sl % NSLOT;
+      double av[2][FM], bv[2][FN];
+      auto fload = [&](int kk, double* a_, double* b_) {
+#pragma unroll
+        for (int a = 0; a < FM; ++a) a_[a] = Lr[slot][kk + fr][wm0 + a * 16 + fc];
+#pragma unroll
+        for (int b = 0; b < FN; ++b) b_[b] = Rr[slot][kk + fr][wn0 + b * 16 + fc];
+      };
+      fload(0, av[0], bv[0]);
       __builtin_amdgcn_sched_barrier(0);
-    }
-    if (kt % FLUSH == FLUSH - 1 || kt + 1 == nk) {
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int kk = 0; kk < BKD; kk += 4) {
+        const int cur = (kk >> 2) & 1;
+        if (kk + 4 < BKD) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-          sum[a][b] += slab[a][b];
-          slab[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], slab[a][b],
+                                                              0, 0, 0);
+        if (kk + 4 < BKD) {
+#pragma unroll
+          for (int g = 0; g < 3; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (sl % FLUSHD == FLUSHD - 1 || sl + 1 == nk) {
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            sum[a][b] += slab[a][b];
+            slab[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+          }
+      }
     }
-    if (kt + 1 < nk) lstore(buf ^ 1);
+    wg_barrier();  // the ring is no longer read (the epilogue's reduction reuses LDS)
+  } else {
+    // Loader: 32 rows x 128 columns per operand = 2048 double2; thread t moves
+    // rows (t / 64) + 8q, q = 0..3, columns 2 (t % 64) and 2 (t % 64) + 1.
+    const int lrow = tid >> 6;
+    const int lcol = (tid & 63) * 2;
+    double2 la[NQ], ra[NQ];
+
+    auto gload = [&](int k0) {
+      if (cols_in && k0 + BK <= n) {
+  #pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const size_t row = (size_t)(k0 + lrow + 8 * q) * n;
+          la[q] = *reinterpret_cast<const double2*>(L + row + i0 + lcol);
+          ra[q] = *reinterpret_cast<const double2*>(R + row + j0 + lcol);
+        }
+      } else {
+  #pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int k = k0 + lrow + 8 * q;
+          const size_t row = (size_t)k * n;
+          const bool kin = k < n;
+          la[q].x = (kin && i0 + lcol < n) ? L[row + i0 + lcol] : 0.0;
+          la[q].y = (kin && i0 + lcol + 1 < n) ? L[row + i0 + lcol + 1] : 0.0;
+          ra[q].x = (kin && j0 + lcol < n) ? R[row + j0 + lcol] : 0.0;
+          ra[q].y = (kin && j0 + lcol + 1 < n) ? R[row + j0 + lcol + 1] : 0.0;
+        }
+      }
+    };
+    auto lstore = [&](int buf) {
+  #pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        *reinterpret_cast<double2*>(&Ls[buf][lrow + 8 * q][lcol]) = la[q];
+        *reinterpret_cast<double2*>(&Rs[buf][lrow + 8 * q][lcol]) = ra[q];
+      }
+    };
+
+    const int nk = (n + BK - 1) / BK;
+    gload(0);
+    lstore(0);
     __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload((kt + 1) * BK);
+      // operands of k-step kk + 4 are read from LDS while the matrix cores
+      // work on k-step kk (an LDS read between pairs of MFMAs), so the two
+      // waves of a SIMD do not both wait on LDS at the start of a step
+      double av[2][FM], bv[2][FN];
+      auto fload = [&](int kk, double* a_, double* b_) {
+  #pragma unroll
+        for (int a = 0; a < FM; ++a) a_[a] = Ls[buf][kk + fr][wm0 + a * 16 + fc];
+  #pragma unroll
+        for (int b = 0; b < FN; ++b) b_[b] = Rs[buf][kk + fr][wn0 + b * 16 + fc];
+      };
+      fload(0, av[0], bv[0]);
+      __builtin_amdgcn_sched_barrier(0);
+  #pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int cur = (kk >> 2) & 1;
+        if (kk + 4 < BK) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
+  #pragma unroll
+        for (int a = 0; a < FM; ++a)
+  #pragma unroll
+          for (int b = 0; b < FN; ++b)
+            slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], slab[a][b],
+                                                              0, 0, 0);
+        if (kk + 4 < BK) {
+  #pragma unroll
+          for (int g = 0; g < 3; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+          }
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (kt % FLUSH == FLUSH - 1 || kt + 1 == nk) {
+  #pragma unroll
+        for (int a = 0; a < FM; ++a)
+  #pragma unroll
+          for (int b = 0; b < FN; ++b) {
+            sum[a][b] += slab[a][b];
+            slab[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+          }
+      }
+      if (kt + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   // Epilogue. Output element r of block (a, b) in this lane (the f64 16x16x4
