@@ -8,9 +8,11 @@ the residual from C and A. A is already resident in HBM when timing starts.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line. Besides the headline schedule (FP64, scaled-identity
-start, triangle products) it times, outside the timed steps, the comparators:
-plain FP64 with full products, the eq. (3) start, and low-precision bulk
-phases; and the oracle on the host cores on a bounded sample.
+start whose scale is tightened by repeated squaring, triangle products) it
+times, outside the timed steps, the comparators: the norm-scaled identity,
+plain FP64 with full products, the eq. (3) start, low-precision bulk phases,
+the learned start; the n = 4096 kernel matrix and the 2000-problem batch; and
+the oracle on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -228,7 +230,9 @@ def main():
     A = torch.from_numpy(a_host).to(dev)
     del a_host
     C = torch.empty_like(A)
-    sched = ipr.ipr_schedule_default(timing=1)
+    # the headline schedule: FP64, scaled identity whose scale is tightened by
+    # repeated squaring (certified bound on lambda_max), triangle products
+    sched = ipr.ipr_schedule_default(timing=1, scale_squarings=6)
     ws = torch.empty(ipr.ipr_workspace_size(n, p, 1, sched), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -272,8 +276,10 @@ def main():
         "config": {"workload": f"householder_spd n={n} p={p} kappa={args.kappa:g} "
                                f"seed={args.seed} tol={tol:g}",
                    "n": n, "p": p, "kappa": args.kappa, "tol": tol,
-                   "schedule": "fp64, scaled-identity start, triangle products"},
+                   "schedule": "fp64, scaled-identity start with the repeated-squaring scale "
+                               "(at most 6 squarings), triangle products"},
         "solve": {"status_all_ok": ok, "iterations": last.iters_fp64, "gemms": last.gemms,
+                  "init_scale": last.init_scale,
                   "residual_true": last.residual_true, "ms_norms": last.ms_norms,
                   "ms_init": last.ms_init, "ms_refine": last.ms_refine,
                   "ms_verify": last.ms_verify},
@@ -313,6 +319,8 @@ def main():
             comps[name] = d
             return d
 
+        d0 = run("fp64_identity_norm_scale_triangle_products")
+        out["speedup_vs_fp64_norm_scale"] = d0["seconds"] / sec
         run("fp64_identity_full_products", triangle=0)
         # eq. (3) start: it cannot reach 1e-10 in FP64 at this condition number;
         # run a bounded number of iterations and model the time of the

@@ -79,6 +79,9 @@ typedef struct {
   const float* mlp_params; /* device, IPR_MLP_NPARAM floats, for IPR_INIT_LEARNED */
   int timing;          /* 1: time every matrix product with device events (ms_gemm, gemm_flops) */
   int tile;            /* ipr_solve_batched: product tile edge 32 or 64; 0 = size-bucket table */
+  int scale_squarings; /* IDENTITY start: up to this many repeated squarings of A / sigma tighten
+                          the scale s of C_0 = s^{-1/p} I (default 0: s = sigma, the norm bound
+                          of eq. (3)); see ipr_solve */
 } ipr_schedule;
 
 typedef struct {

@@ -59,6 +59,33 @@ def start_identity(a: np.ndarray, p: int) -> np.ndarray:
     return s ** (-1.0 / (2 * p)) * np.eye(a.shape[0])
 
 
+def power_scale(a: np.ndarray, p: int, max_squarings: int):
+    """Scale s >= lambda_max(A) of the scaled-identity start from repeated
+    squaring (a reading that extends eq. (3)'s norm bound, not the paper's):
+    with sigma = sqrt(||A||_1 ||A||_inf) and S_k = (A / sigma)^(2^k),
+    b_k = 1.01 sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)) bounds lambda_max
+    (1% margin for rounding). Squaring stops after max_squarings, or after
+    the first squaring whose bound improved on the previous one by less than
+    w = ((1 + 1/p)^p)^(1/(p+1)), the per-product gain of the slow phase.
+    Returns (s, squarings done) with s = min(sigma, b_1, ...)."""
+    sigma = np.sqrt(norm_1(a) * norm_inf(a))
+    worth = ((1.0 + 1.0 / p) ** p) ** (1.0 / (p + 1.0))
+    best = prev = sigma
+    s_k = a / sigma
+    k = 0
+    for k in range(1, max_squarings + 1):
+        s_k = s_k @ s_k
+        b = 1.01 * sigma * (norm_1(s_k) * norm_inf(s_k)) ** (1.0 / 2 ** (k + 1))
+        if not (b > 0.0) or not np.isfinite(b):
+            k -= 1
+            break
+        best = min(best, b)
+        if prev / b < worth:
+            break
+        prev = b
+    return best, k
+
+
 def start_poly(a: np.ndarray, p: int, b) -> np.ndarray:
     """Polynomial start C_0 = sigma^{-1/p} (b0 I + b1 A/sigma + b2 (A/sigma)^2),
     sigma = sqrt(||A||_1 ||A||_inf). b = (1, 0, 0) is the scaled identity."""

@@ -24,7 +24,7 @@ class IprSchedule(ct.Structure):
                 ("triangle", ct.c_int), ("guard_fallback", ct.c_int), ("verify", ct.c_int),
                 ("bulk_switch", ct.c_double), ("stall_ratio", ct.c_double),
                 ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int),
-                ("tile", ct.c_int)]
+                ("tile", ct.c_int), ("scale_squarings", ct.c_int)]
 
 
 class IprResult(ct.Structure):

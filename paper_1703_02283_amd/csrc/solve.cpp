@@ -530,6 +530,36 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     // A / sigma^2 = sigma^{-1/p} q(A / sigma) with q(x) = sigma^{1/p - 1} x
     b[0] = 0.0;
     b[1] = std::pow(sigma, 1.0 / p - 1.0);
+  } else if (init == IPR_INIT_IDENTITY && s.scale_squarings > 0) {
+    // A tighter scale from repeated squaring: lambda_max(A)^(2^k) =
+    // lambda_max(A^(2^k)) <= sqrt(||A^(2^k)||_1 ||A^(2^k)||_inf), a bound that
+    // falls towards lambda_max as k grows. Each squaring is one triangle
+    // product of S_k = (A / sigma)^(2^k) (||S_k|| <= 1: no overflow). It stops
+    // once a squaring improves the bound by less than the factor one product
+    // is worth in the iteration's slow phase, ((1 + 1/p)^p)^(1/(p + 1)). The
+    // 1% margin covers rounding in S_k; a start with lambda_max / s in (1, 2)
+    // would still satisfy eq. (2).
+    const double worth = std::pow(std::pow(1.0 + 1.0 / p, (double)p), 1.0 / (p + 1.0));
+    double* Sb[2] = {sv.Mb[1], sv.Nb[1]};  // free until the first iteration
+    const double* src = dA;
+    double best = sigma, prev = sigma;
+    for (int k = 1; k <= s.scale_squarings; ++k) {
+      Epilogue e;
+      e.alpha = k == 1 ? 1.0 / s2 : 1.0;  // (A / sigma)^2 = A A / sigma^2
+      e.D = Sb[(k - 1) & 1];
+      HIP_TRY(sv.prod.f64(src, src, 1, e));
+      HIP_TRY(norms_1_inf(e.D, n, w.norms_scratch, w.scal + 2, stream));
+      double g[2];
+      if (int rc = read_scalars(w.scal + 2, 2, g, stream)) return rc;
+      const double bk = sigma * std::pow(g[0] * g[1], 1.0 / std::ldexp(1.0, k + 1)) * 1.01;
+      if (!(bk > 0.0) || !std::isfinite(bk)) break;
+      best = std::min(best, bk);
+      if (prev / bk < worth) break;
+      prev = bk;
+      src = e.D;
+    }
+    sc = best;
+    res.init_scale = sc;
   } else if (init == IPR_INIT_LEARNED) {
     // Certified scale: lambda_max(A)^2 = lambda_max(A^2) <= sqrt(||A^2||_1 ||A^2||_inf),
     // one triangle product; then the network's polynomial in units of that bound.
@@ -574,8 +604,10 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     if (!s.guard_fallback)
       return fail(IPR_EGUARD, "ipr_solve: start violates eq. (2) (sup q^p x = %g)", sup_phi);
     res.fallback_used = 1;
+    // the scaled identity at the same scale (sigma, or the learned start's
+    // tighter bound on lambda_max) satisfies eq. (2)
+    if (init != IPR_INIT_LEARNED) sc = sigma;
     init = IPR_INIT_IDENTITY;
-    sc = sigma;
     b[0] = 1.0;
     b[1] = b[2] = 0.0;
     poly_guard(b, p, &sup_phi, &q_pos);

@@ -96,6 +96,26 @@ def test_cfg1_spd256_p2_golden_count(ipr):
     assert it.rel_fro(c, ref.c) <= 1e-10
 
 
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_power_scale_start(ipr, p):
+    # scaled identity with the repeated-squaring bound: the same scale as the
+    # oracle's power_scale, a certified bound on lambda_max, the oracle's
+    # iteration count from that start, and never more iterations than sigma
+    say("power scale p", p)
+    n = 300
+    a, lam, _ = w.spd_log_spectrum(n, 1e4, seed=40 + p)
+    s_ref, k_ref = it.power_scale(a, p, 6)
+    c0, r0 = _solve(ipr, a, p, 1e-10)
+    c, r = _solve(ipr, a, p, 1e-10, scale_squarings=6)
+    assert r.status == ipr.IPR_OK and r0.status == ipr.IPR_OK
+    assert abs(r.init_scale - s_ref) <= 1e-9 * s_ref and k_ref >= 1
+    assert lam.max() <= r.init_scale < np.sqrt(r.norm1 * r.norminf)
+    ref = it.solve(a, p, 1e-10, init=r.init_scale ** (-1.0 / p) * np.eye(n))
+    assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1
+    assert r.iters_fp64 <= r0.iters_fp64
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+
+
 def test_paper_eq3_start(ipr):
     # p = 1 from eq. (3) converges (Newton-Schulz); counts agree with the oracle
     a, _, _ = w.spd_log_spectrum(128, 1e2, seed=7)

@@ -118,3 +118,28 @@ def test_guard_identity_and_paper_starts():
     # a start whose phi overshoots 2 is rejected
     assert not guard.check((2.0, 0.0, 0.0), 1)[0]
     assert not guard.check((1.0, -2.0, 0.0), 2)[0]
+
+
+def test_power_scale_bounds_lambda_max_and_tightens():
+    # A = c I and diagonal A: the norm bound sigma is already lambda_max, the
+    # first squaring's bound (with its 1% margin) is above it, so s = sigma
+    # and squaring stops after one product
+    import workloads as w
+    from oracle import iteration as it
+    s, k = it.power_scale(3.0 * np.eye(5), 2, 6)
+    assert k == 1 and s == 3.0
+    lam = np.array([1e-3, 0.2, 0.5, 2.0])
+    s, k = it.power_scale(np.diag(lam), 3, 6)
+    assert k == 1 and s == 2.0
+    # a matrix whose norm bound is loose: A = Q diag(lam) Q^T with a Haar Q
+    # has sigma well above lambda_max = 1; each squaring brings the bound
+    # closer, and stays >= lambda_max
+    # a general SPD matrix: s >= lambda_max, never above sigma, and no worse
+    # with more squarings allowed
+    a, lam, _ = w.spd_log_spectrum(64, 1e3, seed=3)
+    sig = np.sqrt(it.norm_1(a) * it.norm_inf(a))
+    prev = sig
+    for m in range(0, 5):
+        s, k = it.power_scale(a, 2, m)
+        assert lam.max() <= s <= prev + 1e-15 and k <= m
+        prev = s
