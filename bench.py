@@ -8,8 +8,10 @@ the residual from C and A. A is already resident in HBM when timing starts.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line. Besides the headline schedule (FP64, scaled-identity
-start whose scale is tightened by repeated squaring, triangle products) it
-times, outside the timed steps, the comparators: the norm-scaled identity,
+start whose scale is tightened by repeated squaring, dynamically scaled
+steps, triangle products) it times, outside the timed steps, the
+comparators: the same start with the plain steps of eq. (1), the
+norm-scaled identity,
 plain FP64 with full products, the eq. (3) start, low-precision bulk phases,
 the learned start; the n = 4096 kernel matrix and the 2000-problem batch; and
 the oracle on the host cores on a bounded sample.
@@ -231,8 +233,9 @@ def main():
     del a_host
     C = torch.empty_like(A)
     # the headline schedule: FP64, scaled identity whose scale is tightened by
-    # repeated squaring (certified bound on lambda_max), triangle products
-    sched = ipr.ipr_schedule_default(timing=1, scale_squarings=6)
+    # repeated squaring (certified bound on lambda_max), dynamically scaled
+    # steps (Lanczos estimate of lambda_min), triangle products
+    sched = ipr.ipr_schedule_default(timing=1, scale_squarings=6, dynamic_scaling=1)
     ws = torch.empty(ipr.ipr_workspace_size(n, p, 1, sched), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -277,7 +280,8 @@ def main():
                                f"seed={args.seed} tol={tol:g}",
                    "n": n, "p": p, "kappa": args.kappa, "tol": tol,
                    "schedule": "fp64, scaled-identity start with the repeated-squaring scale "
-                               "(at most 6 squarings), triangle products"},
+                               "(at most 6 squarings), dynamically scaled steps, triangle "
+                               "products"},
         "solve": {"status_all_ok": ok, "iterations": last.iters_fp64, "gemms": last.gemms,
                   "init_scale": last.init_scale,
                   "residual_true": last.residual_true, "ms_norms": last.ms_norms,
@@ -319,6 +323,7 @@ def main():
             comps[name] = d
             return d
 
+        run("fp64_identity_power_scale_unscaled_steps", scale_squarings=6)
         d0 = run("fp64_identity_norm_scale_triangle_products")
         out["speedup_vs_fp64_norm_scale"] = d0["seconds"] / sec
         run("fp64_identity_full_products", triangle=0)

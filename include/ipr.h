@@ -82,6 +82,9 @@ typedef struct {
   int scale_squarings; /* IDENTITY start: up to this many repeated squarings of A / sigma tighten
                           the scale s of C_0 = s^{-1/p} I (default 0: s = sigma, the norm bound
                           of eq. (3)); see ipr_solve */
+  int dynamic_scaling; /* IDENTITY start, FP64: scale every step by a factor chosen from bounds on
+                          the spectrum of M_k, with the lower end estimated by Lanczos (default 0:
+                          the plain iteration of eq. (1)); see ipr_solve */
 } ipr_schedule;
 
 typedef struct {
@@ -104,6 +107,7 @@ typedef struct {
   int lp_gemm_launches;  /* the same for the low-precision products of the bulk phase */
   double ms_lp_gemm;     /* (matrix-core kernel only; the rounding of operands is not included) */
   double lp_gemm_flops;
+  double lmin_est;       /* dynamic_scaling: the Lanczos estimate of lambda_min(A) (0 otherwise) */
 } ipr_result;
 
 #define IPR_MLP_NIN 16

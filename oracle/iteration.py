@@ -86,6 +86,45 @@ def power_scale(a: np.ndarray, p: int, max_squarings: int):
     return best, k
 
 
+def step_map(m, p: int):
+    """One coupled step on an eigenvalue m of M: g(m) = m ((p + 1 - m) / p)^p
+    (the eigenvalue c^p lam of eq. (1)'s scalar recursion, c <- c (p + 1 - m) / p)."""
+    return m * ((p + 1.0 - m) / p) ** p
+
+
+def step_bounds(a: float, b: float, mu: float, p: int):
+    """Bounds on the spectrum of M after a step with scale mu, from bounds
+    [a, b] before it: g rises on (0, 1), peaks at g(1) = 1, falls after."""
+    ga, gb = step_map(mu * a, p), step_map(mu * b, p)
+    nb = 1.0 if mu * a <= 1.0 <= mu * b else max(ga, gb)
+    return min(ga, gb), nb
+
+
+def choose_mu(a: float, b: float, p: int) -> float:
+    """Scale factor of a dynamically scaled step (a reading beyond the paper):
+    the mu in [1, 1.98 / b] maximising min(g(mu a), g(mu b)), the lower end
+    after the step; 1 once a >= 1/2. mu b < 2 keeps the step inside eq. (2).
+    Found by bisection on g(mu a) - g(mu b)."""
+    if not (a > 0.0 and b > 0.0) or a >= 0.5:
+        return 1.0
+    hi = 1.98 / b
+    if hi <= 1.0:
+        return 1.0
+    f = lambda mu: step_map(mu * a, p) - step_map(mu * b, p)
+    if f(hi) <= 0.0:
+        return hi
+    if f(1.0) >= 0.0:
+        return 1.0
+    lo, up = 1.0, hi
+    for _ in range(60):
+        mid = 0.5 * (lo + up)
+        if f(mid) < 0.0:
+            lo = mid
+        else:
+            up = mid
+    return lo
+
+
 def start_poly(a: np.ndarray, p: int, b) -> np.ndarray:
     """Polynomial start C_0 = sigma^{-1/p} (b0 I + b1 A/sigma + b2 (A/sigma)^2),
     sigma = sqrt(||A||_1 ||A||_inf). b = (1, 0, 0) is the scaled identity."""
@@ -155,7 +194,7 @@ def _make_start(a, p, init, poly):
 
 def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 100,
           evaluation: str = "coupled", poly=(1.0, 0.0, 0.0),
-          floor_window: int = 3) -> Result:
+          floor_window: int = 3, dynamic=None) -> Result:
     """Run the iteration of eq. (1) until ||I - C^p A||_F < tol.
 
     evaluation:
@@ -163,6 +202,15 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
                        M <- N (N (... (N M))) (p products); both symmetrised.
       "literal"        X = C^p A; C <- ((p + 1) C - C X) / p (eq. (1) as printed).
       "newton_schulz"  p = 1 only: C <- C (2I - A C), symmetrised (Section II).
+
+    dynamic=(s, theta): the dynamically scaled coupled iteration from the
+    scaled identity at scale s >= lambda_max(A), with theta an estimate of
+    lambda_min(A): bounds [lo, hi] on the spectrum of M_k start at
+    [min(theta / s, 1), 1]; mu_0 = choose_mu(lo, hi) is folded into the start
+    (C_0 = (s / mu_0)^{-1/p} I); step k uses N = ((p + 1) I - mu_k M)/p,
+    C <- mu_k^{1/p} C N, M <- N^p mu_k M, the bounds follow step_bounds, and
+    mu_{k+1} = choose_mu of the new bounds; whenever rho = ||I - M_k||_F < 1,
+    the bounds are narrowed to [1 - rho, 1 + rho].
 
     The returned iteration count is the number of updates applied. Status:
     OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
@@ -178,6 +226,15 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
     n = a.shape[0]
     eye = np.eye(n)
     c = _make_start(a, p, init, poly)
+    mu = 1.0
+    if dynamic is not None:
+        if evaluation != "coupled":
+            raise ValueError("the scaled iteration is a coupled form")
+        s, theta = dynamic
+        lo, hi = min(theta / s, 1.0), 1.0
+        mu0 = choose_mu(lo, hi, p)
+        c = (s / mu0) ** (-1.0 / p) * np.eye(n)
+        lo, hi = lo * mu0, mu0
     m = matpow(c, p) @ a if evaluation == "coupled" else None
     rhos = []
     best = np.inf
@@ -195,6 +252,8 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
         rhos.append(rho)
         if not np.isfinite(rho) or rho > 1e6:
             return Result(c, EDIVERGED, k, rhos)
+        if dynamic is not None and rho < 1.0:
+            lo, hi = max(lo, 1.0 - rho), min(hi, 1.0 + rho)
         if rho < tol:
             tau = true_residual(c, a, p)
             if tau < tol:
@@ -209,7 +268,16 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
                     return Result(c, EFLOOR, k, rhos, true_residual(c, a, p))
         if k == max_iter:
             break
-        if evaluation == "coupled":
+        if evaluation == "coupled" and dynamic is not None:
+            nmat = ((p + 1) * eye - mu * m) / p
+            c = sym(mu ** (1.0 / p) * (c @ nmat))
+            m = mu * m
+            for _ in range(p):
+                m = nmat @ m
+            m = sym(m)
+            lo, hi = step_bounds(lo, hi, mu, p)
+            mu = choose_mu(lo, hi, p)
+        elif evaluation == "coupled":
             nmat = eye + r / p
             c = sym(c @ nmat)
             for _ in range(p):

@@ -24,7 +24,8 @@ class IprSchedule(ct.Structure):
                 ("triangle", ct.c_int), ("guard_fallback", ct.c_int), ("verify", ct.c_int),
                 ("bulk_switch", ct.c_double), ("stall_ratio", ct.c_double),
                 ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int),
-                ("tile", ct.c_int), ("scale_squarings", ct.c_int)]
+                ("tile", ct.c_int), ("scale_squarings", ct.c_int),
+                ("dynamic_scaling", ct.c_int)]
 
 
 class IprResult(ct.Structure):
@@ -37,7 +38,8 @@ class IprResult(ct.Structure):
                 ("ms_init", ct.c_double), ("ms_bulk", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_verify", ct.c_double), ("gemm_launches", ct.c_int), ("ms_gemm", ct.c_double),
                 ("gemm_flops", ct.c_double), ("lp_gemm_launches", ct.c_int),
-                ("ms_lp_gemm", ct.c_double), ("lp_gemm_flops", ct.c_double)]
+                ("ms_lp_gemm", ct.c_double), ("lp_gemm_flops", ct.c_double),
+                ("lmin_est", ct.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

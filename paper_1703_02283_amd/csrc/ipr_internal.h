@@ -65,4 +65,11 @@ hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1
 // X <- (X + X^T) / 2 in place.
 hipError_t symmetrize(double* X, int n, hipStream_t stream);
 
+// Lanczos vector kernels (lanczos.hip)
+hipError_t lz_gemv(const double* A, int n, const double* x, double* y, hipStream_t stream);
+hipError_t lz_dots(const double* Q, int m, int n, const double* w, double* h, hipStream_t stream);
+hipError_t lz_sub(const double* Q, int m, int n, const double* h, double* w, hipStream_t stream);
+hipError_t lz_scale(const double* w, int n, double a, double* v, hipStream_t stream);
+hipError_t lz_start(double* v, int n, hipStream_t stream);
+
 }  // namespace ipr

@@ -261,6 +261,64 @@ struct Prod {
       return fail(IPR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
 
+// One coupled step maps an eigenvalue m of M to g(m) = m ((p + 1 - m) / p)^p.
+double step_map(double m, int p) { return m * std::pow((p + 1.0 - m) / p, (double)p); }
+
+// Bounds [na, nb] on the spectrum of M after one step with scale factor mu
+// from bounds [a, b] before it (g rises on (0, 1), has its maximum 1 at 1
+// and falls on (1, p + 1)).
+void step_bounds(double a, double b, double mu, int p, double* na, double* nb) {
+  const double ga = step_map(mu * a, p), gb = step_map(mu * b, p);
+  *na = std::min(ga, gb);
+  *nb = (mu * a <= 1.0 && 1.0 <= mu * b) ? 1.0 : std::max(ga, gb);
+}
+
+// Scale factor of a step on a spectrum in [a, b]: the mu in [1, 1.98 / b]
+// that maximises the lower end after the step, min(g(mu a), g(mu b)); 1 once
+// a >= 1/2, where the unscaled step is already in its quadratic phase.
+// mu b < 2 keeps the scaled spectrum inside eq. (2)'s region.
+double choose_mu(double a, double b, int p) {
+  if (!(a > 0.0) || !(b > 0.0) || a >= 0.5) return 1.0;
+  const double hi = 1.98 / b;
+  if (hi <= 1.0) return 1.0;
+  auto f = [&](double mu) { return step_map(mu * a, p) - step_map(mu * b, p); };
+  if (f(hi) <= 0.0) return hi;  // the lower end is still the minimum at the cap
+  if (f(1.0) >= 0.0) return 1.0;
+  double lo = 1.0, up = hi;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + up);
+    (f(mid) < 0.0 ? lo : up) = mid;
+  }
+  return lo;
+}
+
+// Smallest eigenvalue of the symmetric tridiagonal matrix (al, be) by
+// bisection on the Sturm count.
+double tridiag_min(const std::vector<double>& al, const std::vector<double>& be) {
+  const int m = (int)al.size();
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  auto below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = al[i] - x - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      cnt += d < 0.0;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (below(mid) >= 1 ? hi : lo) = mid;
+  }
+  return hi;
+}
+
 struct Solver {
   const double* A;
   int n, p, tri;
@@ -276,6 +334,10 @@ struct Solver {
   double* X[2] = {nullptr, nullptr};
   double* Rns = nullptr;  // Newton-Schulz residual (p = 1 after a low-precision phase)
   int slots = 0;          // partial slots holding the current residual's sum of squares
+  // dynamically scaled iteration: M_k enters step k as mu_cur M_k (with C_k as
+  // mu_cur^{1/p} C_k); the product that forms M_{k+1} writes N_{k+1} for
+  // mu_next
+  double mu_cur = 1.0, mu_next = 1.0;
 
   double* C() { return Cb[ci]; }
   double* M() { return Mb[mi]; }
@@ -294,14 +356,15 @@ struct Solver {
     e.S = Nout;
     e.s_init = 1;
     e.sa = (p + 1.0) / p;
-    e.sc = -1.0 / p;
+    e.sc = -mu_next / p;
     e.partial = w.partial;
     e.pd = 1.0;
     return e;
   }
 
   // Mout = L^p B (p products, last with m_epilogue), t = triangle mode.
-  int power_chain(const double* L, const double* B, double* Mout, double* Nout, int t) {
+  int power_chain(const double* L, const double* B, double* Mout, double* Nout, int t,
+                  double alpha1 = 1.0) {
     const double* src = B;
     for (int j = 1; j <= p; ++j) {
       Epilogue e;
@@ -309,6 +372,7 @@ struct Solver {
         e = m_epilogue(Mout, Nout);
       else
         e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
+      if (j == 1) e.alpha = alpha1;
       TRY(prod(L, src, t, e));
       src = e.D;
     }
@@ -349,14 +413,15 @@ struct Solver {
     }
     double* Nc = Nb[ni];
     {
-      Epilogue e;  // C_{k+1} = C_k N_k
+      Epilogue e;  // C_{k+1} = C_k N_k (scaled: mu^{1/p} C_k N_k)
+      e.alpha = mu_cur == 1.0 ? 1.0 : std::pow(mu_cur, 1.0 / p);
       e.D = Cn;
       TRY(prod(Cc, Nc, tri, e));
       if (!tri) TRY(symmetrize(Cn, n, st));
       prod.invalidate(Cn);
     }
-    // M_{k+1} = N_k (N_k (... (N_k M_k))), N_{k+1} from M_{k+1}
-    if (int rc = power_chain(Nc, M(), Mb[mi ^ 1], Nb[ni ^ 1], tri)) return rc;
+    // M_{k+1} = N_k (N_k (... (N_k mu M_k))), N_{k+1} from M_{k+1}
+    if (int rc = power_chain(Nc, M(), Mb[mi ^ 1], Nb[ni ^ 1], tri, mu_cur)) return rc;
     ci ^= 1;
     mi ^= 1;
     ni ^= 1;
@@ -381,6 +446,39 @@ struct Solver {
     TRY(prod.f64(P, A, 0, e));
     TRY(reduce_fro(w.partial, gemm_partial_slots(n, 0), w.scal + 9, st));
     return read_scalars(w.scal + 9, 1, tau, st);
+  }
+
+  // Smallest Ritz value of `steps` Lanczos steps on A with full
+  // reorthogonalisation: an estimate of lambda_min(A) from above. buf holds
+  // (steps + 2) n + steps + 2 doubles.
+  int lanczos_min(int steps, double* buf, double* theta) {
+    double* Q = buf;
+    double* wv = buf + (size_t)(steps + 1) * n;
+    double* h = wv + n;
+    double hs[2];
+    TRY(lz_start(Q, n, st));
+    TRY(lz_dots(Q, 1, n, Q, h, st));
+    if (int rc = read_scalars(h, 1, hs, st)) return rc;
+    TRY(lz_scale(Q, n, 1.0 / std::sqrt(hs[0]), Q, st));
+    std::vector<double> al, be;
+    for (int j = 0; j < steps; ++j) {
+      TRY(lz_gemv(A, n, Q + (size_t)j * n, wv, st));
+      TRY(lz_dots(Q, j + 1, n, wv, h, st));  // h[j] = q_j . A q_j = alpha_j
+      if (int rc = read_scalars(h + j, 1, hs, st)) return rc;
+      al.push_back(hs[0]);
+      TRY(lz_sub(Q, j + 1, n, h, wv, st));
+      TRY(lz_dots(Q, j + 1, n, wv, h, st));  // second pass
+      TRY(lz_sub(Q, j + 1, n, h, wv, st));
+      TRY(lz_dots(wv, 1, n, wv, h, st));
+      if (int rc = read_scalars(h, 1, hs, st)) return rc;
+      const double beta = std::sqrt(hs[0]);
+      if (j + 1 == steps || !(beta > 1e-10 * std::fabs(al[0]))) break;  // invariant subspace
+      be.push_back(beta);
+      TRY(lz_scale(wv, n, 1.0 / beta, Q + (size_t)(j + 1) * n, st));
+    }
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    *theta = tridiag_min(al, be);
+    return IPR_OK;
   }
 
   // M_k = C_k^p A (and N_k) from C_k, or R_k = I - A C_k in Newton-Schulz mode.
@@ -616,6 +714,32 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   for (int i = 0; i < 3; ++i) res.poly_used[i] = b[i];
   if (res.init_scale == 0.0) res.init_scale = sc;
 
+  // Dynamically scaled iteration: bounds [mod_a, mod_b] on the spectrum of
+  // M_k are carried through the scalar map of a step; each step k multiplies
+  // M_k by mu_k >= 1 (C_k by mu_k^{1/p}), chosen to lift the lower end. The
+  // lower end starts from a Lanczos estimate of lambda_min (from above: an
+  // overestimate only makes the factors smaller); the upper end 1 is certified
+  // by the start, and mu_k mod_b < 2 keeps every step inside eq. (2). Once the
+  // residual is below 1 it bounds both ends, and from a lower end of 1/2 on
+  // the steps are unscaled. mu_0 is folded into the start's scale.
+  bool dyn = s.dynamic_scaling && init == IPR_INIT_IDENTITY && s.bulk_dtype == IPR_FP64 &&
+             n >= 32;
+  double mod_a = 0.0, mod_b = 1.0, mu_k = 1.0;
+  if (dyn) {
+    double theta = 0.0;
+    if (int rc = sv.lanczos_min(std::min(24, n - 8), w.m[0], &theta)) return rc;
+    res.lmin_est = theta;
+    dyn = theta > 0.0 && std::isfinite(theta);
+    if (dyn) {
+      mod_a = std::min(theta / sc, 1.0);
+      const double mu0 = choose_mu(mod_a, 1.0, p);
+      sc /= mu0;
+      mod_a *= mu0;
+      mod_b = mu0;
+      res.init_bound = mu0;  // sup of C_0^p lambda over the spectrum bound
+    }
+  }
+
   const double root = std::pow(sc, -1.0 / p);
   if (b[1] == 0.0 && b[2] == 0.0) {
     // scaled identity c I, c = b0 sc^{-1/p}: M_0 = c^p A elementwise
@@ -651,6 +775,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   double rho = 0.0;
   auto restart_identity = [&]() -> int {
     res.fallback_used = 1;
+    sv.mu_cur = sv.mu_next = 1.0;
     sv.ci = sv.mi = sv.ni = 0;
     HIP_TRY(init_identity(dA, n, p, std::pow(s2, -1.0 / (2.0 * p)), 1.0 / sigma, sv.C(),
                           sv.M(), sv.Nb[sv.ni], w.partial, stream));
@@ -699,6 +824,10 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
     res.residual_proxy = rho;
     const bool bad = !std::isfinite(rho) || rho > 1e6;
+    if (dyn && rho < 1.0) {  // ||I - M_k||_2 <= rho bounds the spectrum of M_k
+      mod_a = std::max(mod_a, 1.0 - rho);
+      mod_b = std::min(mod_b, 1.0 + rho);
+    }
     // From a start that commutes with A the residual of the coupled form falls
     // every step until the rounding floor. After a low-precision phase the
     // iterate carries rounding errors that do not commute with A; for p >= 2
@@ -751,6 +880,16 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       break;
     }
     if (k >= kmax) break;
+    if (dyn) {
+      double na, nb;
+      step_bounds(mod_a, mod_b, mu_k, p, &na, &nb);
+      const double mu_n = choose_mu(na, nb, p);
+      sv.mu_cur = mu_k;
+      sv.mu_next = mu_n;
+      mod_a = na;
+      mod_b = nb;
+      mu_k = mu_n;
+    }
     if (int rc = sv.step(ns)) return rc;
   }
   tm.mark(4);

@@ -116,6 +116,30 @@ def test_power_scale_start(ipr, p):
     assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("squarings", [0, 6])
+def test_dynamic_scaling(ipr, p, squarings):
+    # scaled steps from a Lanczos estimate of lambda_min: a Ritz value in the
+    # spectrum, fewer iterations than the plain iteration from the same
+    # start, the oracle's scaled iteration count, and the same root
+    say("dynamic scaling p", p, "squarings", squarings)
+    n = 300
+    a, lam, _ = w.spd_log_spectrum(n, 1e4, seed=70 + p)
+    c0, r0 = _solve(ipr, a, p, 1e-10, scale_squarings=squarings)
+    c, r = _solve(ipr, a, p, 1e-10, scale_squarings=squarings, dynamic_scaling=1)
+    assert r.status == ipr.IPR_OK and r0.status == ipr.IPR_OK
+    assert lam.min() - 1e-12 * lam.max() <= r.lmin_est <= lam.max() * (1 + 1e-12)
+    assert r.iters_fp64 < r0.iters_fp64
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    ref = it.solve(a, p, 1e-10, dynamic=(r.init_scale, r.lmin_est))
+    assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1
+    # A = c I: Lanczos stops after one step at c, and nothing is scaled
+    C, r = ipr.ipr_solve(dev(2.5 * np.eye(64)), p, 1e-10,
+                         schedule=ipr.ipr_schedule_default(dynamic_scaling=1))
+    assert r.status == ipr.IPR_OK and abs(r.lmin_est - 2.5) < 1e-12
+    assert np.allclose(host(C), 2.5 ** (-1.0 / p) * np.eye(64), rtol=1e-13, atol=0)
+
+
 def test_paper_eq3_start(ipr):
     # p = 1 from eq. (3) converges (Newton-Schulz); counts agree with the oracle
     a, _, _ = w.spd_log_spectrum(128, 1e2, seed=7)

@@ -143,3 +143,36 @@ def test_power_scale_bounds_lambda_max_and_tightens():
         s, k = it.power_scale(a, 2, m)
         assert lam.max() <= s <= prev + 1e-15 and k <= m
         prev = s
+
+
+def test_scale_factor_rule_maximises_the_lower_end():
+    from oracle import iteration as it
+    for p in (1, 2, 3, 4):
+        for a, b in ((1e-4, 1.0), (0.01, 0.7), (0.2, 1.0), (0.3, 0.9)):
+            mu = it.choose_mu(a, b, p)
+            assert 1.0 <= mu and mu * b < 2.0
+            grid = np.linspace(1.0, 1.98 / b, 20001)
+            best = np.max(np.minimum(it.step_map(grid * a, p), it.step_map(grid * b, p)))
+            got = min(it.step_map(mu * a, p), it.step_map(mu * b, p))
+            assert got >= best * (1 - 1e-6)
+        assert it.choose_mu(0.6, 1.0, p) == 1.0          # quadratic phase: unscaled
+        # step_bounds encloses g over the scaled interval (dense sampling)
+        for a, b, mu in ((1e-3, 1.0, 1.9), (0.4, 0.8, 1.5), (0.9, 1.0, 1.0)):
+            lo, hi = it.step_bounds(a, b, mu, p)
+            x = np.linspace(mu * a, mu * b, 10001)
+            g = it.step_map(x, p)
+            assert lo <= g.min() + 1e-15 and g.max() <= hi + 1e-15
+            assert abs(lo - g.min()) < 1e-12 and hi - g.max() < 1e-6
+
+
+def test_scaled_iteration_reaches_the_root_in_fewer_steps():
+    import workloads as w
+    from oracle import iteration as it
+    for p in (1, 2, 3):
+        a, lam, _ = w.spd_log_spectrum(120, 1e4, seed=60 + p)
+        s, _ = it.power_scale(a, p, 6)
+        plain = it.solve(a, p, 1e-10, init=s ** (-1.0 / p) * np.eye(120))
+        for theta in (lam.min(), 3.0 * lam.min()):      # exact and overestimated lambda_min
+            r = it.solve(a, p, 1e-10, dynamic=(s, theta))
+            assert r.status == it.OK and r.iters < plain.iters
+            assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
