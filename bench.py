@@ -179,8 +179,10 @@ def batched_runs(ipr, torch, w, dev, tol, reps=3):
     out = {"workload": "batch_recipe(2000): n ~ U{32..512}, p in {1,2,4}, "
                        "kappa logU[10,1e5], seeds 1000+i", "tol": tol,
            "matrices": len(ns), "elements": tot}
-    for name, dt in (("fp64", ipr.IPR_FP64), ("bf16_bulk_then_fp64", ipr.IPR_BF16)):
-        s = ipr.ipr_schedule_default(bulk_dtype=dt)
+    for name, kw in (("fp64_power_scale_scaled_steps",
+                      dict(scale_squarings=6, dynamic_scaling=1)),
+                     ("fp64", {}), ("bf16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_BF16))):
+        s = ipr.ipr_schedule_default(**kw)
         ipr.ipr_solve_batched(A, offs, ns, ps, tol, schedule=s, out=C)   # capture + warm-up
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -195,6 +197,7 @@ def batched_runs(ipr, torch, w, dev, tol, reps=3):
         its = [r.iters_bulk + r.iters_fp64 for r in res]
         # products actually run: (p + 1) per iteration, p for the start's M_0
         # (free for the identity) and p for the final check
+        # (the start's squarings and the Lanczos estimate are not counted)
         prods = sum((p + 1) * (r.iters_bulk + r.iters_fp64) + p for p, r in zip(ps, res))
         fl = sum(((p + 1) * (r.iters_bulk + r.iters_fp64) + p) * 2.0 * n ** 3
                  for n, p, r in zip(ns, ps, res))

@@ -100,14 +100,21 @@ def step_bounds(a: float, b: float, mu: float, p: int):
     return min(ga, gb), nb
 
 
+def mu_cap(p: int) -> float:
+    """Largest scaled top of the spectrum: 1.98 (< 2, eq. (2)); for p = 1 the
+    m with g(m) = m (2 - m) = 1/2, 1 + 1/sqrt(2), so that the step does not
+    push top eigenvalues near 0 (for p >= 2, g(2) >= 1/2)."""
+    return 1.0 + np.sqrt(0.5) if p == 1 else 1.98
+
+
 def choose_mu(a: float, b: float, p: int) -> float:
     """Scale factor of a dynamically scaled step (a reading beyond the paper):
-    the mu in [1, 1.98 / b] maximising min(g(mu a), g(mu b)), the lower end
-    after the step; 1 once a >= 1/2. mu b < 2 keeps the step inside eq. (2).
-    Found by bisection on g(mu a) - g(mu b)."""
+    the mu in [1, mu_cap(p) / b] maximising min(g(mu a), g(mu b)), the lower
+    end after the step; 1 once a >= 1/2. mu b < 2 keeps the step inside
+    eq. (2). Found by bisection on g(mu a) - g(mu b)."""
     if not (a > 0.0 and b > 0.0) or a >= 0.5:
         return 1.0
-    hi = 1.98 / b
+    hi = mu_cap(p) / b
     if hi <= 1.0:
         return 1.0
     f = lambda mu: step_map(mu * a, p) - step_map(mu * b, p)

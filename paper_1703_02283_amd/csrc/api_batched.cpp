@@ -169,6 +169,8 @@ int run_batch(const double* dA, double* dC, const std::vector<BatchItem>& items,
   a.stall_ratio = s.stall_ratio;
   a.max_iter = s.max_iter;
   a.bulk_bf16 = s.bulk_dtype == IPR_BF16 ? 1 : 0;
+  a.squarings = std::max(0, s.scale_squarings);
+  a.dynamic = s.dynamic_scaling ? 1 : 0;
   if (use_graph) {
     if (int rc = launch_graph(a, grid, stream)) return rc;
   } else {
@@ -250,7 +252,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
       r.norm1 = res[i].norm1;
       r.norminf = res[i].norminf;
       r.init_bound = 1.0;
-      r.init_scale = std::sqrt(res[i].norm1 * res[i].norminf);
+      r.init_scale = res[i].init_scale;
+      r.lmin_est = res[i].lmin_est;
       r.poly_used[0] = 1.0;
     }
     if (res[i].status != IPR_OK && status == IPR_OK) status = res[i].status;

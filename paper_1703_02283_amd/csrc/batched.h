@@ -15,6 +15,7 @@ struct BatchItem {
 struct BatchResult {
   int status, iters_bulk, iters_fp64, pad;
   double residual_proxy, residual_true, norm1, norminf;
+  double init_scale, lmin_est;
 };
 
 struct BatchArgs {
@@ -27,6 +28,8 @@ struct BatchArgs {
   BatchResult* results;  // by item index
   double tol, bulk_switch, stall_ratio;
   int max_iter, bulk_bf16;
+  int squarings;  // scale_squarings of the schedule (FP64 items)
+  int dynamic;    // dynamic_scaling of the schedule (FP64 items, n >= 32)
 };
 
 hipError_t batched_launch(const BatchArgs& args, int grid, hipStream_t stream);

@@ -20,6 +20,7 @@
 #include <cstdint>
 
 #include "batched.h"
+#include "scaling.h"
 #include "kernels_common.h"
 
 namespace ipr {
@@ -32,11 +33,14 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 constexpr int NT = 256;
 constexpr int BK = 16;
 
+constexpr int LZ_STEPS = 12;  // Lanczos steps of the lambda_min estimate
+
 struct Smem {
   double L[2][BK][64 + 16];
   double R[2][BK][64 + 16];
   double red[NT / 64];
   double bcast[4];
+  double al[LZ_STEPS], be[LZ_STEPS];
 };
 
 __device__ __forceinline__ double block_sum(double v, Smem& sm) {
@@ -320,24 +324,150 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
     res.residual_proxy = 0.0;
 
     // ---- norms of eq. (3)
-    double cmax = 0.0, rmax = 0.0;
-    for (int j = tid; j < n; j += NT) {  // column sums (coalesced over j)
-      double cs = 0.0;
-      for (int i = 0; i < n; ++i) cs += fabs(b.A[(size_t)i * n + j]);
-      cmax = fmax(cmax, cs);
-    }
-    for (int i = tid >> 6; i < n; i += NT / 64) {  // row sums: one wave per row
-      double rs = 0.0;
-      for (int j = tid & 63; j < n; j += 64) rs += fabs(b.A[(size_t)i * n + j]);
+    auto norms = [&](const double* X, double* o1, double* oi) {
+      double cmax = 0.0, rmax = 0.0;
+      for (int j = tid; j < n; j += NT) {  // column sums (coalesced over j)
+        double cs = 0.0;
+        for (int i = 0; i < n; ++i) cs += fabs(X[(size_t)i * n + j]);
+        cmax = fmax(cmax, cs);
+      }
+      for (int i = tid >> 6; i < n; i += NT / 64) {  // row sums: one wave per row
+        double rs = 0.0;
+        for (int j = tid & 63; j < n; j += 64) rs += fabs(X[(size_t)i * n + j]);
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
-      rmax = fmax(rmax, rs);
-    }
-    const double n1 = block_max(cmax, sm), ninf = block_max(rmax, sm);
+        for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+        rmax = fmax(rmax, rs);
+      }
+      *o1 = block_max(cmax, sm);
+      *oi = block_max(rmax, sm);
+    };
+    double n1, ninf;
+    norms(b.A, &n1, &ninf);
     const double s2 = n1 * ninf, sigma = sqrt(s2);
     res.norm1 = n1;
     res.norminf = ninf;
-    const double c = pow(s2, -1.0 / (2.0 * p)), cp = 1.0 / sigma, inv_p = 1.0 / p;
+    const double inv_p = 1.0 / p;
+    const bool fp64_only = !(args.bulk_bf16 && p == 1);
+
+    // ---- scale of the start: sigma, or the repeated-squaring bound (the
+    // same rule as the single solve: S_k = (A / sigma)^(2^k), b_k = 1.01
+    // sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)), stop when a squaring gains
+    // less than ((1 + 1/p)^p)^(1/(p+1)))
+    double sc = sigma;
+    if (args.squarings > 0 && fp64_only) {
+      const double worth = pow(pow(1.0 + inv_p, (double)p), 1.0 / (p + 1.0));
+      const double* src = b.A;
+      double prev = sigma;
+      for (int k = 1; k <= args.squarings; ++k) {
+        double* dst = b.X[(k - 1) & 1];
+        __syncthreads();
+        if (tid == 0) {
+          ProdDesc d;
+          d.L = src;
+          d.R = src;
+          d.tri = 1;
+          d.lowp = 0;
+          d.e = WEpi();
+          d.e.alpha = k == 1 ? 1.0 / s2 : 1.0;
+          d.e.D = dst;
+          q[0] = d;
+        }
+        __syncthreads();
+        run_products(q, 1, n, tile, &sm);
+        double g1, gi;
+        norms(dst, &g1, &gi);
+        const double bk = sigma * pow(g1 * gi, 1.0 / ldexp(1.0, k + 1)) * 1.01;
+        if (!(bk > 0.0) || !isfinite(bk)) break;
+        sc = fmin(sc, bk);
+        if (prev / bk < worth) break;
+        prev = bk;
+        src = dst;
+      }
+    }
+    res.init_scale = sc;
+    res.lmin_est = 0.0;
+
+    // ---- dynamically scaled steps: lambda_min from LZ_STEPS Lanczos steps
+    // (three-term recurrence; vectors in M[1]), bounds [ma, mb] on the
+    // spectrum of M_k, mu_k from the shared rule; mu_0 folds into the scale
+    const bool dyn0 = args.dynamic && fp64_only && n >= 32;
+    double ma = 0.0, mb = 1.0, mu_k = 1.0;
+    bool dyn = false;
+    if (dyn0) {
+      double* qp = b.M[1];       // q_{j-1}
+      double* qc = b.M[1] + n;   // q_j
+      double* wv = b.M[1] + 2 * (size_t)n;
+      double nrm = 0.0;
+      for (int t = tid; t < n; t += NT) {
+        uint64_t z = (uint64_t)t + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double v = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+        qc[t] = v;
+        qp[t] = 0.0;
+        nrm += v * v;
+      }
+      nrm = sqrt(block_sum(nrm, sm));
+      for (int t = tid; t < n; t += NT) qc[t] /= nrm;
+      double beta = 0.0;
+      int m = 0;
+      for (int j = 0; j < LZ_STEPS; ++j) {
+        __syncthreads();
+        for (int i = tid >> 6; i < n; i += NT / 64) {  // w = A q_j, one wave per row
+          double rs = 0.0;
+          for (int c2 = tid & 63; c2 < n; c2 += 64) rs += b.A[(size_t)i * n + c2] * qc[c2];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+          if ((tid & 63) == 0) wv[i] = rs;
+        }
+        __syncthreads();
+        double pa = 0.0;
+        for (int t = tid; t < n; t += NT) pa += wv[t] * qc[t];
+        const double alpha = block_sum(pa, sm);
+        double pb = 0.0, pr = 0.0;
+        for (int t = tid; t < n; t += NT) {
+          const double v = wv[t] - alpha * qc[t] - beta * qp[t];
+          wv[t] = v;
+          pb += v * v;
+          pr += v * qc[t];
+        }
+        // one reorthogonalisation step against q_j
+        const double r = block_sum(pr, sm);
+        double pb2 = 0.0;
+        for (int t = tid; t < n; t += NT) {
+          const double v = wv[t] - r * qc[t];
+          wv[t] = v;
+          pb2 += v * v;
+        }
+        (void)pb;
+        const double bnew = sqrt(block_sum(pb2, sm));
+        if (tid == 0) sm.al[j] = alpha + r;
+        m = j + 1;
+        if (j + 1 == LZ_STEPS || !(bnew > 1e-10 * fabs(alpha))) break;
+        if (tid == 0) sm.be[j] = bnew;
+        for (int t = tid; t < n; t += NT) {
+          qp[t] = qc[t];
+          qc[t] = wv[t] / bnew;
+        }
+        beta = bnew;
+      }
+      __syncthreads();
+      if (tid == 0) sm.bcast[0] = tridiag_min(sm.al, sm.be, m);
+      __syncthreads();
+      const double theta = sm.bcast[0];
+      __syncthreads();
+      res.lmin_est = theta;
+      if (theta > 0.0 && isfinite(theta)) {
+        dyn = true;
+        ma = fmin(theta / sc, 1.0);
+        const double mu0 = choose_mu(ma, 1.0, p);
+        sc /= mu0;
+        ma *= mu0;
+        mb = mu0;
+      }
+    }
+    const double c = pow(sc, -1.0 / p), cp = 1.0 / sc;
 
     // scaled-identity start: C = c I, M = c^p A, N = ((p+1) I - M)/p
     auto start = [&]() {
@@ -432,6 +562,10 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
         res.status = 4;
         break;
       }
+      if (dyn && rho < 1.0) {  // ||I - M_k||_2 <= rho bounds the spectrum of M_k
+        ma = fmax(ma, 1.0 - rho);
+        mb = fmin(mb, 1.0 + rho);
+      }
       if (rho < args.tol) {
         if (use_ns) {
           res.residual_true = rho;
@@ -486,7 +620,16 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
         rho = ns(true, false);
         continue;
       }
-      // C' = C N; M' = N (N (... (N M))) with N' = ((p+1) I - M') / p
+      // C' = C N; M' = N (N (... (N M))) with N' = ((p+1) I - M') / p; with
+      // scaled steps C' = mu^{1/p} C N, M' = N^p mu M, N' = ((p+1) I - mu' M')/p
+      double mu_n = 1.0;
+      if (dyn) {
+        double na, nb;
+        step_bounds(ma, mb, mu_k, p, &na, &nb);
+        mu_n = choose_mu(na, nb, p);
+        ma = na;
+        mb = nb;
+      }
       __syncthreads();
       if (tid == 0) {
         ProdDesc d;
@@ -495,6 +638,7 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
         d.tri = 1;
         d.lowp = 0;
         d.e = WEpi();
+        d.e.alpha = mu_k == 1.0 ? 1.0 : pow(mu_k, inv_p);
         d.e.D = b.C[ci ^ 1];
         q[0] = d;
         const double* src = b.M[mi];
@@ -505,11 +649,12 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
           m.tri = 1;
           m.lowp = 0;
           m.e = WEpi();
+          if (j == 1) m.e.alpha = mu_k;
           if (j == p) {
             m.e.D = b.M[mi ^ 1];
             m.e.Nout = b.N[ni ^ 1];
-            m.e.np1 = p + 1.0;
-            m.e.inv_p = inv_p;
+            m.e.np1 = (p + 1.0) / mu_n;  // N' = ((p+1)/mu' - M') mu'/p
+            m.e.inv_p = mu_n * inv_p;
             m.e.pd = 1.0;
           } else {
             m.e.D = b.X[(j - 1) & 1];
@@ -520,6 +665,7 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
       }
       __syncthreads();
       rho = sqrt(run_products(q, p + 1, n, tile, &sm));
+      mu_k = mu_n;
       ci ^= 1;
       mi ^= 1;
       ni ^= 1;

@@ -26,6 +26,7 @@
 
 #include "../../include/ipr.h"
 #include "ipr_host.h"
+#include "scaling.h"
 #include "ipr_internal.h"
 #include "learned.h"
 #include "lowp.h"
@@ -261,64 +262,6 @@ struct Prod {
       return fail(IPR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
 
-// One coupled step maps an eigenvalue m of M to g(m) = m ((p + 1 - m) / p)^p.
-double step_map(double m, int p) { return m * std::pow((p + 1.0 - m) / p, (double)p); }
-
-// Bounds [na, nb] on the spectrum of M after one step with scale factor mu
-// from bounds [a, b] before it (g rises on (0, 1), has its maximum 1 at 1
-// and falls on (1, p + 1)).
-void step_bounds(double a, double b, double mu, int p, double* na, double* nb) {
-  const double ga = step_map(mu * a, p), gb = step_map(mu * b, p);
-  *na = std::min(ga, gb);
-  *nb = (mu * a <= 1.0 && 1.0 <= mu * b) ? 1.0 : std::max(ga, gb);
-}
-
-// Scale factor of a step on a spectrum in [a, b]: the mu in [1, 1.98 / b]
-// that maximises the lower end after the step, min(g(mu a), g(mu b)); 1 once
-// a >= 1/2, where the unscaled step is already in its quadratic phase.
-// mu b < 2 keeps the scaled spectrum inside eq. (2)'s region.
-double choose_mu(double a, double b, int p) {
-  if (!(a > 0.0) || !(b > 0.0) || a >= 0.5) return 1.0;
-  const double hi = 1.98 / b;
-  if (hi <= 1.0) return 1.0;
-  auto f = [&](double mu) { return step_map(mu * a, p) - step_map(mu * b, p); };
-  if (f(hi) <= 0.0) return hi;  // the lower end is still the minimum at the cap
-  if (f(1.0) >= 0.0) return 1.0;
-  double lo = 1.0, up = hi;
-  for (int it = 0; it < 60; ++it) {
-    const double mid = 0.5 * (lo + up);
-    (f(mid) < 0.0 ? lo : up) = mid;
-  }
-  return lo;
-}
-
-// Smallest eigenvalue of the symmetric tridiagonal matrix (al, be) by
-// bisection on the Sturm count.
-double tridiag_min(const std::vector<double>& al, const std::vector<double>& be) {
-  const int m = (int)al.size();
-  double lo = al[0], hi = al[0];
-  for (int i = 0; i < m; ++i) {
-    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(be[i]) : 0.0);
-    lo = std::min(lo, al[i] - r);
-    hi = std::max(hi, al[i] + r);
-  }
-  auto below = [&](double x) {  // eigenvalues < x
-    int cnt = 0;
-    double d = 1.0;
-    for (int i = 0; i < m; ++i) {
-      d = al[i] - x - (i > 0 ? be[i - 1] * be[i - 1] / d : 0.0);
-      if (d == 0.0) d = -1e-300;
-      cnt += d < 0.0;
-    }
-    return cnt;
-  };
-  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
-    const double mid = 0.5 * (lo + hi);
-    (below(mid) >= 1 ? hi : lo) = mid;
-  }
-  return hi;
-}
-
 struct Solver {
   const double* A;
   int n, p, tri;
@@ -477,7 +420,7 @@ struct Solver {
       TRY(lz_scale(wv, n, 1.0 / beta, Q + (size_t)(j + 1) * n, st));
     }
     be.resize(al.size() > 0 ? al.size() - 1 : 0);
-    *theta = tridiag_min(al, be);
+    *theta = tridiag_min(al.data(), be.data(), (int)al.size());
     return IPR_OK;
   }
 

@@ -147,3 +147,30 @@ def test_tuner_fills_the_table(ipr):
     t = ipr.ipr_tune_batched(workspace_bytes=2 << 30)
     assert len(t) == ipr.IPR_BATCH_BUCKETS and all(x in (32, 64) for x in t)
     assert ipr.ipr_get_batched_tiles() == t
+
+
+def test_batched_scaled_steps(ipr):
+    # the power scale and the scaled steps inside the persistent kernel: same
+    # roots, fewer iterations, and the oracle's count from the kernel's own
+    # scale and Lanczos estimate (12 steps, three-term recurrence)
+    ns, ps, mats = _case(200)
+    lams = [np.linalg.eigvalsh(a) for a in mats]
+    buf, offs = _pack(mats)
+    _, r0 = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10)
+    s = ipr.ipr_schedule_default(scale_squarings=6, dynamic_scaling=1)
+    C, res = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10, schedule=s)
+    out = _unpack(host(C), offs, ns)
+    for i, (n, p, a, lam) in enumerate(zip(ns, ps, mats, lams)):
+        r = res[i]
+        say("scaled batch item", i, "n", n, "p", p, "iters", r.iters_fp64, "plain", r0[i].iters_fp64,
+            "scale", r.init_scale, "lmin", r.lmin_est)
+        assert r.status == ipr.IPR_OK, (n, p)
+        assert it.rel_fro(out[i], it.eig_root(a, p)) <= 1e-10, (n, p)
+        assert r.iters_fp64 <= r0[i].iters_fp64, (n, p)
+        assert lam.max() <= r.init_scale * (1 + 1e-12)
+        if n >= 32:
+            assert lam.min() - 1e-12 * lam.max() <= r.lmin_est <= lam.max() * (1 + 1e-12)
+            ref = it.solve(a, p, 1e-10, dynamic=(r.init_scale, r.lmin_est))
+            assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1, (n, p)
+        else:
+            assert r.lmin_est == 0.0

@@ -151,11 +151,11 @@ def test_scale_factor_rule_maximises_the_lower_end():
         for a, b in ((1e-4, 1.0), (0.01, 0.7), (0.2, 1.0), (0.3, 0.9)):
             mu = it.choose_mu(a, b, p)
             assert 1.0 <= mu and mu * b < 2.0
-            grid = np.linspace(1.0, 1.98 / b, 20001)
+            grid = np.linspace(1.0, it.mu_cap(p) / b, 20001)
             best = np.max(np.minimum(it.step_map(grid * a, p), it.step_map(grid * b, p)))
             got = min(it.step_map(mu * a, p), it.step_map(mu * b, p))
             assert got >= best * (1 - 1e-6)
-        assert it.choose_mu(0.6, 1.0, p) == 1.0          # quadratic phase: unscaled
+            assert it.choose_mu(0.6, 1.0, p) == 1.0          # quadratic phase: unscaled
         # step_bounds encloses g over the scaled interval (dense sampling)
         for a, b, mu in ((1e-3, 1.0, 1.9), (0.4, 0.8, 1.5), (0.9, 1.0, 1.0)):
             lo, hi = it.step_bounds(a, b, mu, p)
@@ -176,3 +176,17 @@ def test_scaled_iteration_reaches_the_root_in_fewer_steps():
             r = it.solve(a, p, 1e-10, dynamic=(s, theta))
             assert r.status == it.OK and r.iters < plain.iters
             assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
+
+
+def test_scaled_iteration_keeps_the_p1_floor():
+    # p = 1 at kappa = 6e4: with the scaled top capped at 1 + 1/sqrt(2) the
+    # scaled iteration reaches 1e-10 like the plain one (a cap of 1.98 left
+    # it at ~1.9e-10)
+    import workloads as w
+    from oracle import iteration as it
+    a, lam, _ = w.spd_log_spectrum(200, 6e4, seed=10)
+    s, _ = it.power_scale(a, 1, 6)
+    plain = it.solve(a, 1, 1e-10, init=s ** (-1.0) * np.eye(200))
+    r = it.solve(a, 1, 1e-10, dynamic=(s, 1.5 * lam.min()))
+    assert plain.status == it.OK and r.status == it.OK and r.iters < plain.iters
+    assert r.residual_true < 2.0 * plain.residual_true
