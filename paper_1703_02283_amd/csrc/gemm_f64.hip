@@ -48,10 +48,24 @@ constexpr int FLUSH = 2;       // slabs (2 x 32 = 64 k) per slab accumulator
 constexpr int NQ = BK / 8;     // loader passes (8 rows of 128 per pass)
 // interior tiles: k slabs of 16 rows in a ring of 4 LDS slots (the same LDS
 // as the two 32-row buffers of the edge path), filled by direct loads
-constexpr int BKD = 16;
-constexpr int NSLOT = 4;
-constexpr int FLUSHD = 4;      // 4 x 16 = 64 k per slab accumulator
+#ifndef IPR_F64_BKD
+#define IPR_F64_BKD 16
+#endif
+constexpr int BKD = IPR_F64_BKD;
+constexpr int NSLOT = 2 * BK / BKD;
+constexpr int DEPTH = NSLOT - 1;           // slabs in flight ahead of the one being read
+constexpr int RPW = BKD / 8;               // k rows per wave and operand per slab
+constexpr int LPS = 2 * RPW;               // direct loads per lane per slab
+constexpr int FLUSHD = 64 / BKD;           // slabs per 64-k slab accumulator
 static_assert(NSLOT * BKD == 2 * BK, "the two paths share the LDS buffers");
+
+// s_waitcnt with only the vector-memory count waited on: vmcnt in bits 3:0
+// and 15:14, expcnt (6:4) = 7 and lgkmcnt (11:8) = 15 left open
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -96,16 +110,16 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
 
   if (cols_in && n % BKD == 0) {
-    // Interior tile: each wave moves k rows 2w and 2w + 1 of L and R per slab
-    // straight into LDS (64 lanes x 16 bytes = one 128-double row), two slabs
-    // ahead of the matrix cores; only the slab about to be read is waited for.
+    // Interior tile: each wave moves RPW k rows of L and R per slab straight
+    // into LDS (64 lanes x 16 bytes = one 128-double row), DEPTH slabs ahead
+    // of the matrix cores; only the slab about to be read is waited for.
     double (*Lr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Ls[0][0][0]);
     double (*Rr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Rs[0][0][0]);
     auto issue = [&](int sl) {
       const int slot = sl % NSLOT;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int row = 2 * wave + h;
+      for (int h = 0; h < RPW; ++h) {
+        const int row = RPW * wave + h;
         const size_t g = (size_t)(sl * BKD + row) * n + 2 * lane;
         // LDS destinations as plain wave-uniform addresses
         const uint32_t ll = __builtin_amdgcn_readfirstlane(
@@ -119,18 +133,22 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
       }
     };
     const int nk = n / BKD;
-    issue(0);
-    if (nk > 1) issue(1);
-    if (nk > 2) issue(2);
+    for (int d = 0; d < DEPTH && d < nk; ++d) issue(d);
     for (int sl = 0; sl < nk; ++sl) {
-      // (s_waitcnt: vmcnt in bits 3:0, expcnt 6:4 = 7, lgkmcnt 11:8 = 15;
-      // a slab is 4 loads per lane)
+      // wait for slab sl: the slabs issued after it may stay in flight
       const int after = nk - 1 - sl;
-      if (after >= 2) __builtin_amdgcn_s_waitcnt(0x0F78);       // vmcnt(8)
-      else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4)
-      else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
-      wg_barrier();  // slab sl is in LDS for every wave; slot (sl + 3) % 4 is free
-      if (sl + 3 < nk) issue(sl + 3);
+      if constexpr (DEPTH >= 3) {
+        if (after >= 2) wait_vm<2 * LPS>();
+        else if (after == 1) wait_vm<LPS>();
+        else wait_vm<0>();
+      } else if constexpr (DEPTH == 2) {
+        if (after >= 1) wait_vm<LPS>();
+        else wait_vm<0>();
+      } else {
+        wait_vm<0>();
+      }
+      wg_barrier();  // slab sl is in LDS for every wave; slot (sl + DEPTH) % NSLOT is free
+      if (sl + DEPTH < nk) issue(sl + DEPTH);
       const int slot = sl % NSLOT;
       double av[2][FM], bv[2][FN];
       auto fload = [&](int kk, double* a_, double* b_) {
