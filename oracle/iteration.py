@@ -59,17 +59,19 @@ def start_identity(a: np.ndarray, p: int) -> np.ndarray:
     return s ** (-1.0 / (2 * p)) * np.eye(a.shape[0])
 
 
-def power_scale(a: np.ndarray, p: int, max_squarings: int):
+def power_scale(a: np.ndarray, p: int, max_squarings: int, scaled_steps: bool = False):
     """Scale s >= lambda_max(A) of the scaled-identity start from repeated
     squaring (a reading that extends eq. (3)'s norm bound, not the paper's):
     with sigma = sqrt(||A||_1 ||A||_inf) and S_k = (A / sigma)^(2^k),
     b_k = 1.01 sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)) bounds lambda_max
-    (1% margin for rounding). Squaring stops after max_squarings, or after
-    the first squaring whose bound improved on the previous one by less than
-    w = ((1 + 1/p)^p)^(1/(p+1)), the per-product gain of the slow phase.
+    (1% margin for rounding). Squaring stops after max_squarings, or once the
+    next squaring is predicted (square root of the last improvement b_{k-1}/b_k)
+    to improve the bound by less than what one product buys in the slow phase:
+    w = ((1 + 1/p)^p c)^(1/(p+1)), c = mu_cap(p) with scaled steps, else 1.
     Returns (s, squarings done) with s = min(sigma, b_1, ...)."""
     sigma = np.sqrt(norm_1(a) * norm_inf(a))
-    worth = ((1.0 + 1.0 / p) ** p) ** (1.0 / (p + 1.0))
+    grow = (1.0 + 1.0 / p) ** p * (mu_cap(p) if scaled_steps else 1.0)
+    worth = grow ** (1.0 / (p + 1.0))
     best = prev = sigma
     s_k = a / sigma
     k = 0
@@ -80,7 +82,7 @@ def power_scale(a: np.ndarray, p: int, max_squarings: int):
             k -= 1
             break
         best = min(best, b)
-        if prev / b < worth:
+        if np.sqrt(prev / b) < worth:
             break
         prev = b
     return best, k

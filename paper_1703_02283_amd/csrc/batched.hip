@@ -351,11 +351,11 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
 
     // ---- scale of the start: sigma, or the repeated-squaring bound (the
     // same rule as the single solve: S_k = (A / sigma)^(2^k), b_k = 1.01
-    // sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)), stop when a squaring gains
-    // less than ((1 + 1/p)^p)^(1/(p+1)))
+    // sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)), stop when the next squaring
+    // is predicted to gain less than squaring_worth)
     double sc = sigma;
     if (args.squarings > 0 && fp64_only) {
-      const double worth = pow(pow(1.0 + inv_p, (double)p), 1.0 / (p + 1.0));
+      const double worth = squaring_worth(p, args.dynamic && n >= 32);
       const double* src = b.A;
       double prev = sigma;
       for (int k = 1; k <= args.squarings; ++k) {
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
         const double bk = sigma * pow(g1 * gi, 1.0 / ldexp(1.0, k + 1)) * 1.01;
         if (!(bk > 0.0) || !isfinite(bk)) break;
         sc = fmin(sc, bk);
-        if (prev / bk < worth) break;
+        if (sqrt(prev / bk) < worth) break;  // the next squaring would not pay
         prev = bk;
         src = dst;
       }

@@ -30,6 +30,17 @@ __host__ __device__ inline void step_bounds(double a, double b, double mu, int p
 // g(2) >= 1/2 already.
 __host__ __device__ inline double mu_cap(int p) { return p == 1 ? 1.0 + sqrt(0.5) : 1.98; }
 
+// A squaring of the start's scale bound (one product) pays when it lowers
+// the bound by more than what one product buys in the slow phase of the
+// iteration, where the lower end of the spectrum grows by (1 + 1/p)^p per
+// step of p + 1 products, or by mu_cap (1 + 1/p)^p with scaled steps.
+// Successive squarings improve the bound by about the square root of the
+// previous improvement, so squaring stops once that prediction falls below.
+__host__ __device__ inline double squaring_worth(int p, bool scaled_steps) {
+  const double grow = pow(1.0 + 1.0 / p, (double)p) * (scaled_steps ? mu_cap(p) : 1.0);
+  return pow(grow, 1.0 / (p + 1.0));
+}
+
 // Scale factor of a step on a spectrum in [a, b]: the mu in [1, mu_cap / b]
 // that maximises the lower end after the step, min(g(mu a), g(mu b)); 1 once
 // a >= 1/2, where the unscaled step is already in its quadratic phase.

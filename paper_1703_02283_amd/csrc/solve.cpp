@@ -576,11 +576,11 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     // lambda_max(A^(2^k)) <= sqrt(||A^(2^k)||_1 ||A^(2^k)||_inf), a bound that
     // falls towards lambda_max as k grows. Each squaring is one triangle
     // product of S_k = (A / sigma)^(2^k) (||S_k|| <= 1: no overflow). It stops
-    // once a squaring improves the bound by less than the factor one product
-    // is worth in the iteration's slow phase, ((1 + 1/p)^p)^(1/(p + 1)). The
+    // once the next squaring is predicted to gain less than one product's
+    // worth (squaring_worth). The
     // 1% margin covers rounding in S_k; a start with lambda_max / s in (1, 2)
     // would still satisfy eq. (2).
-    const double worth = std::pow(std::pow(1.0 + 1.0 / p, (double)p), 1.0 / (p + 1.0));
+    const double worth = squaring_worth(p, s.dynamic_scaling != 0);
     double* Sb[2] = {sv.Mb[1], sv.Nb[1]};  // free until the first iteration
     const double* src = dA;
     double best = sigma, prev = sigma;
@@ -595,7 +595,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       const double bk = sigma * std::pow(g[0] * g[1], 1.0 / std::ldexp(1.0, k + 1)) * 1.01;
       if (!(bk > 0.0) || !std::isfinite(bk)) break;
       best = std::min(best, bk);
-      if (prev / bk < worth) break;
+      if (std::sqrt(prev / bk) < worth) break;  // the next squaring would not pay
       prev = bk;
       src = e.D;
     }
