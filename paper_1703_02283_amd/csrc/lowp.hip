@@ -73,6 +73,28 @@ __device__ inline uint8_t bits_e4m3(double y) {
   return s | (uint8_t)(((e + 7) << 3) | m);
 }
 
+constexpr int BT = 256;                 // output tile edge
+constexpr int KB = 64;                  // bytes of k per row and stage
+constexpr int NSTG = 4;                 // LDS ring depth
+constexpr int STG_BYTES = BT * KB;      // one operand, one stage
+
+// Physical chunk of logical 16-byte chunk `chunk` in LDS row `row`. Any 8
+// consecutive rows read at one logical chunk cover a 128-byte period, and
+// any 16 a 256-byte period, without two lanes on one bank.
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return chunk ^ ((row >> 1) & 3) ^ (((row >> 3) & 1) * 3);
+}
+
+// Byte offset of the 16-byte piece of row i that starts at byte kb of the
+// row, in the blocked layout of the codes: for each 256-row block and each
+// 64-byte stage of k, the 256 x 64 bytes the product kernel moves into LDS
+// for that stage are stored contiguously and in LDS order (rows of 4 chunks,
+// swizzled), so a wave's load is one contiguous kilobyte.
+__host__ __device__ inline size_t lp_block_offset(int i, int kb, int nst) {
+  const int r = i % BT, c = (kb % KB) / 16;
+  return ((size_t)(i / BT) * nst + kb / KB) * (size_t)(BT * KB) + (size_t)r * KB + 16 * swz(r, c);
+}
+
 // One workgroup per 128 x 128 input tile (tr, tc): exponent from the tile's
 // largest magnitude, then codes of X^T into Q (ldq = padded order).
 template <typename T>
@@ -138,7 +160,9 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
         wd[k] = (uint32_t)src[4 * k] | ((uint32_t)src[4 * k + 1] << 8) |
                 ((uint32_t)src[4 * k + 2] << 16) | ((uint32_t)src[4 * k + 3] << 24);
     }
-    *reinterpret_cast<uint4*>(Q + (size_t)(c0 + cl) * ldq + r0 + pc * PER) =
+    const int nst = ldq * (int)sizeof(T) / KB;
+    *reinterpret_cast<uint4*>(reinterpret_cast<uint8_t*>(Q) +
+                              lp_block_offset(c0 + cl, (r0 + pc * PER) * (int)sizeof(T), nst)) =
         make_uint4(wd[0], wd[1], wd[2], wd[3]);
   }
 }
@@ -161,21 +185,9 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
 //   multiplies the A fragments of k-tile t by 2^(eL + eR - Sref) <= 1 (exact
 //   unless it underflows fp16, i.e. below 2^-24 of the largest k-tile's scale).
 //   bf16 is unscaled.
-constexpr int BT = 256;                 // output tile edge
-constexpr int KB = 64;                  // bytes of k per row and stage
-constexpr int NSTG = 4;                 // LDS ring depth
-constexpr int STG_BYTES = BT * KB;      // one operand, one stage
-
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
-
-// Physical chunk of logical 16-byte chunk `chunk` in LDS row `row`. Any 8
-// consecutive rows read at one logical chunk cover a 128-byte period, and
-// any 16 a 256-byte period, without two lanes on one bank.
-__device__ __forceinline__ int swz(int row, int chunk) {
-  return chunk ^ ((row >> 1) & 3) ^ (((row >> 3) & 1) * 3);
-}
 
 template <int V>
 struct Ic {
@@ -244,21 +256,22 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
 
   // loader: instruction q of wave w fills rows 64 w + 16 q .. + 15 of a stage;
   // lane l's 16 bytes land at row (l / 4), physical chunk l % 4
-  const int lrow = lane >> 2;
+  // the blocked layout holds each stage's 256 x 64 bytes contiguously and in
+  // LDS order: lane l of instruction q copies bytes (64 w + 16 q) 64 + 16 l
+  const int nst_all = (int)(ldb / KB);
   const uint8_t* gA[4];
   const uint8_t* gB[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = 64 * wave + 16 * q + lrow;
-    const int c = swz(row, lane & 3);
-    gA[q] = Lt + (size_t)(i0 + row) * ldb + 16 * c;
-    gB[q] = Rt + (size_t)(j0 + row) * ldb + 16 * c;
+    const size_t in_block = (size_t)(64 * wave + 16 * q) * KB + 16 * lane;
+    gA[q] = Lt + (size_t)bi * nst_all * (BT * KB) + in_block;
+    gB[q] = Rt + (size_t)bj * nst_all * (BT * KB) + in_block;
   }
   auto issue = [&](auto S, int st) {
     constexpr int sl = decltype(S)::value;
     uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
     uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
-    const size_t kb0 = (size_t)st * KB;
+    const size_t kb0 = (size_t)st * (BT * KB);   // stage st's block
     // LDS destinations as plain addresses (wave-uniform, in scalar registers)
     const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)as);
     const uint32_t lb = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)bs);
