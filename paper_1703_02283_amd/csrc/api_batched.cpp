@@ -37,7 +37,7 @@ int grid_size(int batch) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return std::max(1, std::min(batch, cus));  // one resident workgroup per CU
+  return std::max(1, std::min(batch, kBatchWgPerCu * cus));  // all resident at once
 }
 
 struct Layout {

@@ -6,6 +6,9 @@
 
 namespace ipr {
 
+// Resident workgroups per CU (the kernel's launch bound and the grid size).
+constexpr int kBatchWgPerCu = 2;
+
 struct BatchItem {
   int64_t a_off;   // element offset of A_i (and C_i) in the packed buffers
   int64_t s_off;   // element offset of its 7 n_i^2 scratch matrices

@@ -293,7 +293,7 @@ struct Bufs {
   double* X[2];
 };
 
-__global__ __launch_bounds__(NT, 1) void batched_kernel(BatchArgs args) {
+__global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs args) {
   __shared__ Smem sm;
   __shared__ __attribute__((aligned(16))) char qraw[QMAX * sizeof(ProdDesc)];
   ProdDesc* q = reinterpret_cast<ProdDesc*>(qraw);
