@@ -13,16 +13,20 @@
 //    accumulator chained over all n of k loses accuracy with the chain length
 //    (measured on gfx950: 6.6x the rms error of the two-level sum at n = 1024),
 //    and in the iteration that error shows up as a residual floor several
-//    times higher; flushing every 64 k costs under 2% of the instruction time.
+//    times higher. In the interior loop the adds of a finished chain sit
+//    between the first instructions of the next one, whose first product
+//    starts from a zero accumulator.
 //  * The left operand is read as L^T: for D = L^T R both operands stream rows
 //    k of L and R, 128 contiguous doubles (1 KiB) per row and tile, so every
 //    global load is a fully coalesced row segment and neither operand needs a
 //    transpose on its way into LDS. Every left operand of the iteration is
 //    symmetric, so L^T R = L R there.
-//  * K slabs of 32 double-buffered in LDS (one barrier per slab; 144 KiB, one
-//    workgroup per CU); the row pitch
-//    of 144 doubles puts consecutive k rows half a bank sweep apart, so the
-//    16-lane row reads of the MFMA operands are conflict free.
+//  * Interior tiles (n a multiple of 64): 16-row k slabs in a 4-slot LDS ring
+//    (128 KiB, one workgroup per CU) filled by direct global-to-LDS loads
+//    three slabs ahead; one barrier per slab. Edge tiles: 32-row slabs
+//    staged through registers, double-buffered in the same LDS. Rows are
+//    stored unpadded: each 16-lane row of an operand read is served on its
+//    own, and a pitch of 144 doubles measured no faster.
 //  * XCD-aware tile order: workgroup w runs on XCD w % 8, so w is remapped to
 //    give each XCD a contiguous run of 8 x 8-tile super-tiles, whose 16 row and
 //    column panels then stay in that XCD's L2 while its tiles are in flight.
@@ -42,22 +46,20 @@ constexpr int WM = 64;         // wave tile rows
 constexpr int WN = 32;         // wave tile columns
 constexpr int FM = WM / 16;    // 16 x 16 blocks per wave, rows
 constexpr int FN = WN / 16;    // 16 x 16 blocks per wave, columns
-constexpr int LDP = BM + 16;   // LDS row pitch in doubles
+constexpr int LDP = BM;        // LDS row pitch in doubles (unpadded: see the header)
 constexpr int NT = 512;        // threads per workgroup (8 waves)
 constexpr int FLUSH = 2;       // slabs (2 x 32 = 64 k) per slab accumulator
 constexpr int NQ = BK / 8;     // loader passes (8 rows of 128 per pass)
 // interior tiles: k slabs of 16 rows in a ring of 4 LDS slots (the same LDS
 // as the two 32-row buffers of the edge path), filled by direct loads
-#ifndef IPR_F64_BKD
-#define IPR_F64_BKD 16
-#endif
-constexpr int BKD = IPR_F64_BKD;
-constexpr int NSLOT = 2 * BK / BKD;
+constexpr int BKD = 16;
+constexpr int NSLOT = 2 * BK / BKD;        // 4
 constexpr int DEPTH = NSLOT - 1;           // slabs in flight ahead of the one being read
 constexpr int RPW = BKD / 8;               // k rows per wave and operand per slab
 constexpr int LPS = 2 * RPW;               // direct loads per lane per slab
 constexpr int FLUSHD = 64 / BKD;           // slabs per 64-k slab accumulator
 static_assert(NSLOT * BKD == 2 * BK, "the two paths share the LDS buffers");
+static_assert(DEPTH == 3 && FLUSHD == 4, "the interior loop is written for these");
 
 // s_waitcnt with only the vector-memory count waited on: vmcnt in bits 3:0
 // and 15:14, expcnt (6:4) = 7 and lgkmcnt (11:8) = 15 left open
@@ -109,86 +111,112 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   const int fc = lane & 15;   // m (or n) index of this lane's operand element
   const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
 
-  if (cols_in && n % BKD == 0) {
+  if (cols_in && n % 64 == 0) {
     // Interior tile: each wave moves RPW k rows of L and R per slab straight
     // into LDS (64 lanes x 16 bytes = one 128-double row), DEPTH slabs ahead
     // of the matrix cores; only the slab about to be read is waited for.
     double (*Lr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Ls[0][0][0]);
     double (*Rr)[BKD][LDP] = reinterpret_cast<double (*)[BKD][LDP]>(&Rs[0][0][0]);
+    // Everything but the lane offset of a direct load is wave-uniform: the LDS
+    // destinations and row addresses are formed in scalar registers (a per-lane
+    // address computation followed by a read-back to a scalar register cost
+    // about 3% of the kernel's time).
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const uint32_t lds_l = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(lds_void*)&Lr[0][0][0]);
+    const uint32_t lds_r = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(lds_void*)&Rr[0][0][0]);
+    const uint32_t lane_b = 16u * (uint32_t)lane;
     auto issue = [&](int sl) {
       const int slot = sl % NSLOT;
 #pragma unroll
       for (int h = 0; h < RPW; ++h) {
-        const int row = RPW * wave + h;
-        const size_t g = (size_t)(sl * BKD + row) * n + 2 * lane;
-        // LDS destinations as plain wave-uniform addresses
-        const uint32_t ll = __builtin_amdgcn_readfirstlane(
-            (uint32_t)(uintptr_t)(lds_void*)&Lr[slot][row][0]);
-        const uint32_t lr = __builtin_amdgcn_readfirstlane(
-            (uint32_t)(uintptr_t)(lds_void*)&Rr[slot][row][0]);
-        __builtin_amdgcn_global_load_lds((const void*)(L + g + i0), (lds_void*)(uintptr_t)ll, 16,
-                                         0, 0);
-        __builtin_amdgcn_global_load_lds((const void*)(R + g + j0), (lds_void*)(uintptr_t)lr, 16,
-                                         0, 0);
+        const int row = RPW * wave_u + h;
+        const uint32_t off = (uint32_t)((slot * BKD + row) * LDP) * 8u;
+        const size_t grow = (size_t)(sl * BKD + row) * n;
+        const char* gl = reinterpret_cast<const char*>(L + grow + i0);
+        const char* gr_ = reinterpret_cast<const char*>(R + grow + j0);
+        __builtin_amdgcn_global_load_lds((const void*)(gl + lane_b),
+                                         (lds_void*)(uintptr_t)(lds_l + off), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(gr_ + lane_b),
+                                         (lds_void*)(uintptr_t)(lds_r + off), 16, 0, 0);
       }
     };
-    const int nk = n / BKD;
+    const int nk = n / BKD;  // a multiple of FLUSHD
     for (int d = 0; d < DEPTH && d < nk; ++d) issue(d);
-    for (int sl = 0; sl < nk; ++sl) {
-      // wait for slab sl: the slabs issued after it may stay in flight
-      const int after = nk - 1 - sl;
-      if constexpr (DEPTH >= 3) {
+    // The slab loop is unrolled by the 64-k chain length so that the first
+    // k-step of every chain is its own code: there each block's finished
+    // chain is added to the running sums and its first product starts from
+    // zero (no separate pass that clears the accumulators).
+    for (int sg = 0; sg < nk; sg += FLUSHD) {
+#pragma unroll
+      for (int s4 = 0; s4 < FLUSHD; ++s4) {
+        const int sl = sg + s4;
+        // wait for slab sl: the slabs issued after it may stay in flight
+        const int after = nk - 1 - sl;
         if (after >= 2) wait_vm<2 * LPS>();
         else if (after == 1) wait_vm<LPS>();
         else wait_vm<0>();
-      } else if constexpr (DEPTH == 2) {
-        if (after >= 1) wait_vm<LPS>();
-        else wait_vm<0>();
-      } else {
-        wait_vm<0>();
-      }
-      wg_barrier();  // slab sl is in LDS for every wave; slot (sl + DEPTH) % NSLOT is free
-      if (sl + DEPTH < nk) issue(sl + DEPTH);
-      const int slot = sl % NSLOT;
-      double av[2][FM], bv[2][FN];
-      auto fload = [&](int kk, double* a_, double* b_) {
+        wg_barrier();  // slab sl is in LDS for every wave; slot (sl + DEPTH) % NSLOT is free
+        if (sl + DEPTH < nk) issue(sl + DEPTH);
+        const int slot = sl % NSLOT;
+        double av[2][FM], bv[2][FN];
+        auto fload = [&](int kk, double* a_, double* b_) {
 #pragma unroll
-        for (int a = 0; a < FM; ++a) a_[a] = Lr[slot][kk + fr][wm0 + a * 16 + fc];
+          for (int a = 0; a < FM; ++a) a_[a] = Lr[slot][kk + fr][wm0 + a * 16 + fc];
 #pragma unroll
-        for (int b = 0; b < FN; ++b) b_[b] = Rr[slot][kk + fr][wn0 + b * 16 + fc];
-      };
-      fload(0, av[0], bv[0]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int kk = 0; kk < BKD; kk += 4) {
-        const int cur = (kk >> 2) & 1;
-        if (kk + 4 < BKD) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-          for (int b = 0; b < FN; ++b)
-            slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], slab[a][b],
-                                                              0, 0, 0);
-        if (kk + 4 < BKD) {
-#pragma unroll
-          for (int g = 0; g < 3; ++g) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
-          }
-          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-        }
+          for (int b = 0; b < FN; ++b) b_[b] = Rr[slot][kk + fr][wn0 + b * 16 + fc];
+        };
+        fload(0, av[0], bv[0]);
         __builtin_amdgcn_sched_barrier(0);
-      }
-      if (sl % FLUSHD == FLUSHD - 1 || sl + 1 == nk) {
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+        for (int kk = 0; kk < BKD; kk += 4) {
+          const int cur = (kk >> 2) & 1;
+          if (kk + 4 < BKD) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
+          if (s4 == 0 && kk == 0) {
 #pragma unroll
-          for (int b = 0; b < FN; ++b) {
-            sum[a][b] += slab[a][b];
-            slab[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+              for (int b = 0; b < FN; ++b) {
+                sum[a][b] += slab[a][b];
+                slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                    av[cur][a], bv[cur][b], (v4d){0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+              }
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // 4 FP64 adds
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+            }
+#pragma unroll
+            for (int g = 0; g < 5; ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+          } else {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+              for (int b = 0; b < FN; ++b)
+                slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b],
+                                                                  slab[a][b], 0, 0, 0);
+            if (kk + 4 < BKD) {
+#pragma unroll
+              for (int g = 0; g < 3; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+              }
+              __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            }
           }
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) sum[a][b] += slab[a][b];
     wg_barrier();  // the ring is no longer read (the epilogue's reduction reuses LDS)
   } else {
     // Loader: 32 rows x 128 columns per operand = 2048 double2; thread t moves
