@@ -96,6 +96,25 @@ def test_cfg1_spd256_p2_golden_count(ipr):
     assert it.rel_fro(c, ref.c) <= 1e-10
 
 
+@pytest.mark.parametrize("p,kappa,tol", [(1, 10.0, 1e-8), (2, 100.0, 1e-10),
+                                         (3, 10.0, 1e-10), (2, 1e4, 1e-10)])
+def test_last_step_without_m_update(ipr, p, kappa, tol):
+    # Once (p + 1)/(2p) rho_k^2 bounds the next residual below tol, the last
+    # step forms C only and the check of the true residual replaces the M
+    # update: (p + 1) products per iteration in all instead of p more. The
+    # oracle's residual history shows the bound holds, with a wide margin.
+    say("last step p", p, "kappa", kappa, "tol", tol)
+    a, lam, _ = w.spd_log_spectrum(256, kappa, seed=90 + p)
+    ref = it.solve(a, p, tol)
+    assert (p + 1) / (2 * p) * ref.rho[-2] ** 2 < 0.2 * tol
+    c, r = _solve(ipr, a, p, tol)
+    assert r.status == ipr.IPR_OK and r.residual_true < tol
+    assert r.iters_fp64 == ref.iters
+    assert r.gemms == (p + 1) * r.iters_fp64
+    assert it.rel_fro(c, ref.c) <= 1e-10
+    assert np.array_equal(c, c.T)
+
+
 @pytest.mark.parametrize("p", [1, 2, 4])
 def test_power_scale_start(ipr, p):
     # scaled identity with the repeated-squaring bound: the same scale as the
