@@ -91,7 +91,8 @@ typedef struct {
   int status;          /* ipr_status of the solve */
   int iters_bulk;      /* updates applied in the low-precision bulk phase */
   int iters_fp64;      /* updates applied in FP64 */
-  int fallback_used;   /* 1 if the requested start failed the guard and IDENTITY was used */
+  int fallback_used;   /* 1 if IDENTITY was used instead: the requested start failed the
+                          guard, or the low-precision phase failed and FP64 restarted */
   int gemms;           /* matrix products launched (all phases) */
   double residual_proxy; /* last tracked ||I - C^p A||_F */
   double residual_true;  /* ||I - C^p A||_F computed from C and A (NaN if not verified) */

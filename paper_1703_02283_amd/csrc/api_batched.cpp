@@ -246,6 +246,7 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
       r.status = res[i].status;
       r.iters_bulk = res[i].iters_bulk;
       r.iters_fp64 = res[i].iters_fp64;
+      r.fallback_used = res[i].fallback_used;
       r.residual_proxy = res[i].residual_proxy;
       r.residual_true = res[i].residual_true >= 0 ? res[i].residual_true
                                                    : std::numeric_limits<double>::quiet_NaN();

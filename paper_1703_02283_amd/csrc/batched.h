@@ -16,7 +16,7 @@ struct BatchItem {
 };
 
 struct BatchResult {
-  int status, iters_bulk, iters_fp64, pad;
+  int status, iters_bulk, iters_fp64, fallback_used;
   double residual_proxy, residual_true, norm1, norminf;
   double init_scale, lmin_est;
 };

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     BatchResult res;
     res.status = 2;  // EMAXITER unless set below
     res.iters_bulk = res.iters_fp64 = 0;
-    res.pad = 0;
+    res.fallback_used = 0;
     res.residual_true = -1.0;
     res.residual_proxy = 0.0;
 
@@ -527,8 +527,8 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     bool use_ns = false;
     if (lp) {
       rho = ns(false, true);
-      double best = 1e300;
-      int stale = 0;
+      double best = 1e300, top = 1e300;
+      int stale = 0, flat = 0;
       for (kb = 0; kb < args.max_iter; ++kb) {
         if (!(rho <= 1e6)) break;
         if (rho < args.bulk_switch) break;
@@ -539,16 +539,29 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
           } else if (++stale >= 2) {
             break;
           }
+        } else if (rho < top) {  // above 1 the residual must still fall every step
+          top = rho;
+          flat = 0;
+        } else if (++flat >= 2) {
+          break;
         }
         rho = ns(true, true);
       }
       res.iters_bulk = kb;
-      if (rho <= 1e6) {
+      // FP64 Newton-Schulz steps from the bulk result converge when its FP64
+      // residual is below 1; otherwise (or after divergence) the FP64
+      // iteration starts again from the scaled identity.
+      bool keep = rho <= 1e6;
+      if (keep) {
         rho = ns(false, false);  // FP64 residual of the bulk result
+        keep = rho < 1.0;
+      }
+      if (keep) {
         use_ns = true;
-      } else {                   // bulk diverged: FP64 from the identity again
+      } else {
         ci = 0;
         rho = start();
+        res.fallback_used = 1;
       }
     }
 

@@ -735,8 +735,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     sv.prod.lowp_dtype = s.bulk_dtype;
     if (p == 1)  // Newton-Schulz bulk: R_0 = I - A C_0
       if (int rc = sv.recompute(true)) return rc;
-    double best = std::numeric_limits<double>::infinity();
-    int stale = 0;
+    double best = std::numeric_limits<double>::infinity(), top = best;
+    int stale = 0, flat = 0;
     for (kb = 0; kb < s.max_iter; ++kb) {
       if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
       if (!std::isfinite(rho) || rho > 1e6) break;
@@ -748,6 +748,11 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
         } else if (++stale >= 2) {
           break;
         }
+      } else if (rho < top) {  // above 1 the residual must still fall every step
+        top = rho;
+        flat = 0;
+      } else if (++flat >= 2) {
+        break;
       }
       if (int rc = sv.step(p == 1)) return rc;
     }
@@ -806,7 +811,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
         floor = true;
       }
     }
-    if (lowp && !lp_restart && (bad || rising || floor)) {
+    // (a bulk result whose FP64 residual is not below 1 is no start either)
+    if (lowp && !lp_restart && (bad || rising || floor || (k == 0 && !(rho < 1.0)))) {
       lp_restart = true;
       ns = false;
       if (int rc = restart_identity()) return rc;

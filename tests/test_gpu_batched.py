@@ -114,6 +114,25 @@ def test_batched_bf16_bulk_for_p1(ipr):
             assert r.iters_bulk > 0
 
 
+def test_batched_bf16_bulk_restarts_in_fp64(ipr):
+    # at kappa = 1e4 the bf16 phase cannot bring ||I - A C|| below 1
+    # (kappa u_bf16 > 1): the FP64 iteration starts again from the scaled
+    # identity and reaches the root as the plain FP64 solve does
+    ns = [96, 160, 64]
+    ps = [1, 1, 1]
+    mats = [w.spd_log_spectrum(n, 1e4, seed=120 + i)[0] for i, n in enumerate(ns)]
+    buf, offs = _pack(mats)
+    s = ipr.ipr_schedule_default(bulk_dtype=ipr.IPR_BF16)
+    C, res = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10, schedule=s)
+    C64, res64 = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10)
+    cs = _unpack(host(C), offs, ns)
+    for n, a, c, r, r64 in zip(ns, mats, cs, res, res64):
+        assert r.status == ipr.IPR_OK, r.as_dict()
+        assert r.fallback_used == 1 and r.iters_bulk > 0
+        assert r.iters_fp64 == r64.iters_fp64
+        assert it.rel_fro(c, it.eig_root(a, 1)) <= 1e-10
+
+
 def test_batched_recipe_sample(ipr):
     # 200 items of the uneven batch recipe (n in [32, 512], p in {1, 2, 4},
     # kappa log-uniform in [10, 1e5]); every item against the definition.
