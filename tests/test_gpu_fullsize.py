@@ -25,15 +25,19 @@ def ipr():
     return m
 
 
+@pytest.mark.parametrize("headline", [False, True])
 @pytest.mark.parametrize("kappa", [1e4, 1e2])
-def test_householder_16384_p2(ipr, kappa):
+def test_householder_16384_p2(ipr, kappa, headline):
+    # headline = the schedule the bench times (power-scale start, scaled
+    # steps); otherwise the default schedule, whose count the oracle fixes
     import torch
     n, p = 16384, 2
-    say("full size householder n", n, "kappa", kappa)
+    say("full size householder n", n, "kappa", kappa, "headline", headline)
     a, lam = w.householder_spd(n, kappa, seed=0)
     A = dev(a)
     del a
-    C, res = ipr.ipr_solve(A, p, 1e-10)
+    kw = dict(scale_squarings=6, dynamic_scaling=1) if headline else {}
+    C, res = ipr.ipr_solve(A, p, 1e-10, schedule=ipr.ipr_schedule_default(**kw))
     say("  status", res.status, "iters", res.iters_fp64, "residual", res.residual_true)
     c = host(C)
     del A, C
@@ -45,7 +49,12 @@ def test_householder_16384_p2(ipr, kappa):
     assert res.status == ipr.IPR_OK, res.as_dict()
     assert res.residual_true < 1e-10
     assert err <= 1e-10
-    assert abs(res.iters_fp64 - g) <= 1
+    if headline:
+        assert res.iters_fp64 < g       # fewer iterations than the plain iteration
+        assert lam.max() <= res.init_scale < math.sqrt(res.norm1 * res.norminf)
+        assert lam.min() * (1 - 1e-12) <= res.lmin_est <= lam.max()
+    else:
+        assert abs(res.iters_fp64 - g) <= 1
     assert np.array_equal(c[:64, :], c[:, :64].T)
 
 
