@@ -15,7 +15,11 @@ constexpr int kMlpScratchPerSample = 3 + 64 + 64 + 3 + 64 + 64 + 64 + 64 + 1;
 
 hipError_t features(const double* Apack, const int64_t* off, const int* ns, const int* ps,
                     int batch, float* feat, hipStream_t stream);
-hipError_t features_one(const double* A, int n, int p, float* feat, hipStream_t stream);
+// Features of one matrix; norms (device) holds ||A||_1, ||A||_inf, and part
+// (device) features_one_part(n) doubles of scratch.
+int features_one_part(int n);
+hipError_t features_one(const double* A, int n, int p, const double* norms, double* part,
+                        float* feat, hipStream_t stream);
 hipError_t mlp_forward(const float* params, const float* X, int batch, float* Y, float* Z1,
                        float* Z2, hipStream_t stream);
 hipError_t mlp_train_step(float* params, float* grad, float* m, float* v, const float* X,

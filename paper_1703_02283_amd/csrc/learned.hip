@@ -14,6 +14,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NI = 16, NH = 64, NO = 3;
+constexpr int kFeatRowsMin = 256;  // from this order on the single-matrix features use many workgroups
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NI, OFF_W2 = OFF_B1 + NH,
               OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH,
               NPARAM = OFF_B3 + NO;
@@ -46,6 +47,38 @@ __device__ double block_red(double v, int op, double* sh) {
     r = op == 0 ? r + sh[w] : (op == 1 ? fmax(r, sh[w]) : fmin(r, sh[w]));
   __syncthreads();
   return r;
+}
+
+// Row statistics of a matrix (sums, then maxima and minima) from which the
+// features follow: sum d, sum d^2, sum |d|, sum o, sum r, sum of squares, max
+// off-diagonal |A_ij|, min d, max d, min (d_i - o_i) (unscaled A).
+struct RowStats {
+  double sd, sd2, sabsd, so, sr, sq, offmax, dmin, dmax, gmin;
+};
+constexpr int kRowStats = 10;
+
+__device__ void write_features(float* f, int n, int pm, double n1, double ninf,
+                               const RowStats& r) {
+  const double s = sqrt(n1 * ninf);
+  const double t1 = r.sd / s / n, t2 = r.sq / (s * s) / n;
+  const double mean_d = r.sd / n;
+  const double var_d = fmax(r.sd2 / n - mean_d * mean_d, 0.0);
+  f[0] = (float)(log2((double)n) / 10.0);
+  f[1] = (float)(pm / 4.0);
+  f[2] = (float)t1;
+  f[3] = (float)t2;
+  f[4] = (float)log10(t1);
+  f[5] = (float)log10(t2);
+  f[6] = (float)(t1 * t1 / t2);
+  f[7] = (float)(r.dmin / s);
+  f[8] = (float)(r.dmax / s);
+  f[9] = (float)log10(fmax(r.dmin / s, 1e-30));
+  f[10] = (float)(r.gmin / s);
+  f[11] = (float)(r.sr / s / n);
+  f[12] = (float)(r.so / r.sabsd);
+  f[13] = (float)(n > 1 ? r.offmax / s : 0.0);
+  f[14] = (float)(sqrt(var_d) / mean_d);
+  f[15] = (float)log10(s);
 }
 
 // One workgroup per matrix. With s = sqrt(||A||_1 ||A||_inf), B = A / s,
@@ -103,38 +136,104 @@ __global__ __launch_bounds__(NT) void features_kernel(const double* __restrict__
     gmin = fmin(gmin, d - o);
   }
   const double ninf = block_red(rmax, 1, sh);
-  sd = block_red(sd, 0, sh);
-  sd2 = block_red(sd2, 0, sh);
-  sabsd = block_red(sabsd, 0, sh);
-  so = block_red(so, 0, sh);
-  sr = block_red(sr, 0, sh);
-  sq = block_red(sq, 0, sh);
-  offmax = block_red(offmax, 1, sh);
-  dmin = block_red(dmin, 2, sh);
-  dmax = block_red(dmax, 1, sh);
-  gmin = block_red(gmin, 2, sh);
+  RowStats r;
+  r.sd = block_red(sd, 0, sh);
+  r.sd2 = block_red(sd2, 0, sh);
+  r.sabsd = block_red(sabsd, 0, sh);
+  r.so = block_red(so, 0, sh);
+  r.sr = block_red(sr, 0, sh);
+  r.sq = block_red(sq, 0, sh);
+  r.offmax = block_red(offmax, 1, sh);
+  r.dmin = block_red(dmin, 2, sh);
+  r.dmax = block_red(dmax, 1, sh);
+  r.gmin = block_red(gmin, 2, sh);
+  if (tid == 0) write_features(feat + (size_t)m * NI, n, pm, n1, ninf, r);
+}
+
+// One large matrix: block b takes rows 16 b .. 16 b + 15 (one wave per row,
+// four rows per wave) and writes its RowStats (kRowStats doubles) to part.
+__global__ __launch_bounds__(NT) void features_rows_kernel(const double* __restrict__ A, int n,
+                                                           double* __restrict__ part) {
+  __shared__ double sh[NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double sd = 0.0, sd2 = 0.0, sabsd = 0.0, so = 0.0, sr = 0.0, sq = 0.0, offmax = 0.0,
+         dmin = 1e308, dmax = -1e308, gmin = 1e308;
+  for (int k = 0; k < 4; ++k) {
+    const int i = blockIdx.x * 16 + 4 * k + wave;
+    if (i >= n) break;
+    double rs = 0.0, q2 = 0.0, om = 0.0;
+    for (int j = lane; j < n; j += 64) {
+      const double v = A[(size_t)i * n + j];
+      rs += fabs(v);
+      q2 += v * v;
+      if (j != i) om = fmax(om, fabs(v));
+    }
+    rs = wsum(rs);
+    q2 = wsum(q2);
+    om = wmax(om);
+    const double d = A[(size_t)i * n + i];
+    const double o = rs - fabs(d);
+    sd += d;
+    sd2 += d * d;
+    sabsd += fabs(d);
+    so += o;
+    sr += rs;
+    sq += q2;
+    offmax = fmax(offmax, om);
+    dmin = fmin(dmin, d);
+    dmax = fmax(dmax, d);
+    gmin = fmin(gmin, d - o);
+  }
+  const double v[kRowStats] = {block_red(sd, 0, sh),     block_red(sd2, 0, sh),
+                               block_red(sabsd, 0, sh),  block_red(so, 0, sh),
+                               block_red(sr, 0, sh),     block_red(sq, 0, sh),
+                               block_red(offmax, 1, sh), block_red(dmin, 2, sh),
+                               block_red(dmax, 1, sh),   block_red(gmin, 2, sh)};
+  if (tid == 0)
+    for (int k = 0; k < kRowStats; ++k) part[(size_t)blockIdx.x * kRowStats + k] = v[k];
+}
+
+// Combines the nb blocks' RowStats (in a fixed order) with ||A||_1 and
+// ||A||_inf (device, norms[0..1]) into the 16 features.
+__global__ __launch_bounds__(NT) void features_finish_kernel(const double* __restrict__ part,
+                                                             int nb, int n, int pm,
+                                                             const double* __restrict__ norms,
+                                                             float* __restrict__ feat) {
+  __shared__ double sh[NT / 64];
+  const int tid = threadIdx.x;
+  double acc[kRowStats];
+  for (int k = 0; k < kRowStats; ++k) acc[k] = k == 7 || k == 9 ? 1e308 : (k == 8 ? -1e308 : 0.0);
+  for (int b = tid; b < nb; b += NT) {
+    const double* q = part + (size_t)b * kRowStats;
+    for (int k = 0; k < 6; ++k) acc[k] += q[k];
+    acc[6] = fmax(acc[6], q[6]);
+    acc[7] = fmin(acc[7], q[7]);
+    acc[8] = fmax(acc[8], q[8]);
+    acc[9] = fmin(acc[9], q[9]);
+  }
+  for (int k = 0; k < kRowStats; ++k) {
+    const int op = k < 6 ? 0 : (k == 7 || k == 9 ? 2 : 1);
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double u = __shfl_xor(v, off, 64);
+      v = op == 0 ? v + u : (op == 1 ? fmax(v, u) : fmin(v, u));
+    }
+    acc[k] = block_red(v, op, sh);
+  }
   if (tid == 0) {
-    const double s = sqrt(n1 * ninf);
-    const double t1 = sd / s / n, t2 = sq / (s * s) / n;
-    const double mean_d = sd / n;
-    const double var_d = fmax(sd2 / n - mean_d * mean_d, 0.0);
-    float* f = feat + (size_t)m * NI;
-    f[0] = (float)(log2((double)n) / 10.0);
-    f[1] = (float)(pm / 4.0);
-    f[2] = (float)t1;
-    f[3] = (float)t2;
-    f[4] = (float)log10(t1);
-    f[5] = (float)log10(t2);
-    f[6] = (float)(t1 * t1 / t2);
-    f[7] = (float)(dmin / s);
-    f[8] = (float)(dmax / s);
-    f[9] = (float)log10(fmax(dmin / s, 1e-30));
-    f[10] = (float)(gmin / s);
-    f[11] = (float)(sr / s / n);
-    f[12] = (float)(so / sabsd);
-    f[13] = (float)(n > 1 ? offmax / s : 0.0);
-    f[14] = (float)(sqrt(var_d) / mean_d);
-    f[15] = (float)log10(s);
+    RowStats r;
+    r.sd = acc[0];
+    r.sd2 = acc[1];
+    r.sabsd = acc[2];
+    r.so = acc[3];
+    r.sr = acc[4];
+    r.sq = acc[5];
+    r.offmax = acc[6];
+    r.dmin = acc[7];
+    r.dmax = acc[8];
+    r.gmin = acc[9];
+    write_features(feat, n, pm, norms[0], norms[1], r);
   }
 }
 
@@ -339,9 +438,21 @@ hipError_t features(const double* Apack, const int64_t* off, const int* ns, cons
   return hipGetLastError();
 }
 
-hipError_t features_one(const double* A, int n, int p, float* feat, hipStream_t stream) {
-  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NT), 0, stream, A, nullptr, nullptr, nullptr,
-                     n, p, feat);
+int features_one_part(int n) { return n < kFeatRowsMin ? 0 : ((n + 15) / 16) * kRowStats; }
+
+hipError_t features_one(const double* A, int n, int p, const double* norms, double* part,
+                        float* feat, hipStream_t stream) {
+  if (n < kFeatRowsMin) {
+    hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NT), 0, stream, A, nullptr, nullptr, nullptr,
+                       n, p, feat);
+    return hipGetLastError();
+  }
+  // one workgroup cannot stream a large matrix at HBM speed (909 ms for
+  // n = 16384): rows are spread over n / 16 workgroups
+  const int nb = (n + 15) / 16;
+  hipLaunchKernelGGL(features_rows_kernel, dim3(nb), dim3(NT), 0, stream, A, n, part);
+  hipLaunchKernelGGL(features_finish_kernel, dim3(1), dim3(NT), 0, stream, part, nb, n, p, norms,
+                     feat);
   return hipGetLastError();
 }
 

@@ -617,7 +617,10 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     HIP_TRY(norms_1_inf(Gm, n, w.norms_scratch, w.scal + 2, stream));
     float* feat = reinterpret_cast<float*>(w.scal + 16);   // 16 floats
     float* yout = reinterpret_cast<float*>(w.scal + 24);   // 3 floats
-    HIP_TRY(features_one(dA, n, p, feat, stream));
+    // w.partial holds max(n, tile count) doubles, more than the features need
+    if ((size_t)features_one_part(n) > std::max<size_t>(n, 1))
+      return fail(IPR_EARG, "ipr_solve: feature scratch too small");
+    HIP_TRY(features_one(dA, n, p, w.scal, w.partial, feat, stream));
     HIP_TRY(mlp_forward(s.mlp_params, feat, 1, yout, nullptr, nullptr, stream));
     double hs[32];
     if (int rc = read_scalars(w.scal, 32, hs, stream)) return rc;

@@ -139,6 +139,32 @@ def test_learned_start_guard_and_fallback(ipr):
 
 
 @pytest.mark.skipif(_weights() is None, reason="no trained weights in the package")
+@pytest.mark.parametrize("n", [200, 512, 1000])
+def test_learned_start_uses_the_batched_features(ipr, n):
+    # The single solve computes its features with one workgroup below n = 256
+    # and with n / 16 workgroups from there on; either way the polynomial it
+    # uses is the network's output on the features of ipr_features (pinned to
+    # the oracle above), up to float rounding and the guard's common scale.
+    import torch
+    theta = torch.tensor(_weights()).cuda()
+    a, _ = w.batch_matrix(n, 3e3, 11 + n)
+    f = ipr.ipr_features(dev(a.ravel()), [0], [n], [2])
+    assert np.allclose(f.cpu().numpy()[0], ft.features(a, 2), rtol=2e-6, atol=2e-6)
+    y = ipr.ipr_mlp_forward(theta, f).cpu().numpy()[0].astype(np.float64)
+    b = np.array([np.exp(y[0]), y[1], y[2]])
+    if abs(b[1]) < 0.05 * b[0] and abs(b[2]) < 0.05 * b[0]:
+        b[1] = b[2] = 0.0
+    s = ipr.ipr_schedule_default(init=ipr.IPR_INIT_LEARNED, mlp_params=theta)
+    C, r = ipr.ipr_solve(dev(a), 2, 1e-10, schedule=s)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 0
+    used = np.array(list(r.poly_used))
+    t = used[0] / b[0]
+    assert 0.0 < t <= 1.0 + 1e-5
+    assert np.allclose(used, t * b, rtol=1e-4, atol=1e-5 * b[0])
+    assert it.rel_fro(host(C), it.eig_root(a, 2)) <= 1e-10
+
+
+@pytest.mark.skipif(_weights() is None, reason="no trained weights in the package")
 def test_learned_start_gains_on_heldout_sample(ipr):
     import torch
     from paper_1703_02283_amd import train_start as ts
