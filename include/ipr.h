@@ -52,10 +52,27 @@ typedef enum {
   IPR_INIT_IDENTITY = 0,  /* C_0 = (||A||_1 ||A||_inf)^{-1/(2p)} I: satisfies eq. (2) for every SPD A */
   IPR_INIT_PAPER_EQ3 = 1, /* eq. (3): C_0 = A^T / (||A||_1 ||A||_inf) */
   IPR_INIT_POLY = 2,      /* C_0 = s^{-1/p} (b0 I + b1 A/s + b2 (A/s)^2), s = sqrt(||A||_1 ||A||_inf) */
-  IPR_INIT_LEARNED = 3    /* POLY in units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4}
+  IPR_INIT_LEARNED = 3,   /* POLY in units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4}
                              (>= lambda_max, one product), with (log b0, b1, b2) predicted by the
                              MLP in schedule.mlp_params from ipr_features; checked against eq. (2) */
+  IPR_INIT_USER = 4       /* C_0 = the contents of dC on entry (a warm start). It must be symmetric;
+                             for the coupled and literal orders also a function of A (a polynomial
+                             in A, or the root of a matrix with the same eigenvectors), for
+                             Newton-Schulz any C_0 with ||I - A C_0||_2 < 1. Accepted when the
+                             start's residual ||I - C_0^p A||_F (resp. ||I - A C_0||_F) is below 1,
+                             which implies eq. (2); otherwise guard_fallback applies */
 } ipr_init;
+
+/* Order in which the products of eq. (1) are evaluated (Section II). */
+typedef enum {
+  IPR_EVAL_COUPLED = 0,       /* M_k = C_k^p A carried along: N_k = ((p+1) I - M_k)/p,
+                                 C_{k+1} = C_k N_k, M_{k+1} = N_k^p M_k (p + 1 products; default) */
+  IPR_EVAL_LITERAL = 1,       /* eq. (1) as printed: X = C_k^p A, C_{k+1} = ((p+1) C_k - C_k X)/p,
+                                 full products, no symmetrisation (p + 1 products; a diagnostic:
+                                 rounding errors grow beyond small condition numbers) */
+  IPR_EVAL_NEWTON_SCHULZ = 2  /* p = 1 only: R_k = I - A C_k (full product), C_{k+1} = C_k + C_k R_k
+                                 (2 products; removes errors that do not commute with A) */
+} ipr_evaluation;
 
 /* Arithmetic type of the bulk (early) iterations. FP64 refinement follows a
  * low-precision bulk phase (Section III: low precision first, precise last). */
@@ -85,6 +102,8 @@ typedef struct {
   int dynamic_scaling; /* IDENTITY start, FP64: scale every step by a factor chosen from bounds on
                           the spectrum of M_k, with the lower end estimated by Lanczos (default 0:
                           the plain iteration of eq. (1)); see ipr_solve */
+  int evaluation;      /* ipr_evaluation (default COUPLED); LITERAL and NEWTON_SCHULZ need the FP64
+                          bulk dtype and ipr_solve (not the batched solver) */
 } ipr_schedule;
 
 typedef struct {
@@ -128,7 +147,8 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
 
 /* A^{-1/p} of one SPD matrix (Section II, eqs. (1)-(3)).
  *   dA    device, n x n float64, symmetric (read only)
- *   dC    device, n x n float64: receives A^{-1/p} (exactly symmetric)
+ *   dC    device, n x n float64: receives A^{-1/p} (exactly symmetric, except with the
+ *         LITERAL order); with IPR_INIT_USER it holds C_0 on entry
  *   tol   stop when ||I - C^p A||_F < tol (> 0)
  *   s     schedule (NULL = defaults)
  *   out   host, receives the result record (may be NULL)

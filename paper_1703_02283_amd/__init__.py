@@ -8,7 +8,8 @@ There is no CPU fallback: if the library is not built, every call raises.
 """
 from .binding import (  # noqa: F401
     IPR_OK, IPR_EARG, IPR_EMAXITER, IPR_EFLOOR, IPR_EDIVERGED, IPR_EHIP, IPR_EGUARD,
-    IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED,
+    IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED, IPR_INIT_USER,
+    IPR_EVAL_COUPLED, IPR_EVAL_LITERAL, IPR_EVAL_NEWTON_SCHULZ,
     IPR_FP64, IPR_BF16, IPR_FP16, IPR_FP8_E4M3, IPR_MLP_NPARAM,
     IprSchedule, IprResult, IprError, library_path, load,
     ipr_schedule_default, ipr_workspace_size, ipr_solve, ipr_solve_batched, ipr_gemm,

@@ -12,7 +12,8 @@ import os
 import torch
 
 IPR_OK, IPR_EARG, IPR_EMAXITER, IPR_EFLOOR, IPR_EDIVERGED, IPR_EHIP, IPR_EGUARD = range(7)
-IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED = range(4)
+IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED, IPR_INIT_USER = range(5)
+IPR_EVAL_COUPLED, IPR_EVAL_LITERAL, IPR_EVAL_NEWTON_SCHULZ = range(3)
 IPR_FP64, IPR_BF16, IPR_FP16, IPR_FP8_E4M3 = range(4)
 IPR_MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3
 STATUS_NAMES = {0: "OK", 1: "EARG", 2: "EMAXITER", 3: "EFLOOR", 4: "EDIVERGED", 5: "EHIP",
@@ -25,7 +26,7 @@ class IprSchedule(ct.Structure):
                 ("bulk_switch", ct.c_double), ("stall_ratio", ct.c_double),
                 ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int),
                 ("tile", ct.c_int), ("scale_squarings", ct.c_int),
-                ("dynamic_scaling", ct.c_int)]
+                ("dynamic_scaling", ct.c_int), ("evaluation", ct.c_int)]
 
 
 class IprResult(ct.Structure):
@@ -181,12 +182,15 @@ def ipr_solve(A, p, tol, schedule=None, out=None, workspace=None, stream=None,
               raise_on=(IPR_EARG, IPR_EHIP, IPR_EGUARD)):
     """A^{-1/p} of the SPD matrix A (n x n float64 device tensor).
     Returns (C, IprResult); numerical outcomes other than OK are reported in
-    result.status (and raise only when listed in ``raise_on``)."""
+    result.status (and raise only when listed in ``raise_on``). With
+    init=IPR_INIT_USER, ``out`` holds C_0 on entry."""
     _need(A, torch.float64, name="A")
     n = A.shape[0]
     if A.dim() != 2 or A.shape[1] != n:
         raise ValueError("A must be square")
     sch = schedule if schedule is not None else ipr_schedule_default()
+    if sch.init == IPR_INIT_USER and out is None:
+        raise ValueError("init=IPR_INIT_USER takes C_0 in `out`")
     C = out if out is not None else torch.empty_like(A)
     _need(C, torch.float64, (n, n), "out")
     need = ipr_workspace_size(n, p, 1, sch)

@@ -217,6 +217,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
     return fail(IPR_EARG, "ipr_solve_batched: only the scaled-identity start is supported");
   if (s.bulk_dtype != IPR_FP64 && s.bulk_dtype != IPR_BF16)
     return fail(IPR_EARG, "ipr_solve_batched: bulk dtype must be FP64 or BF16");
+  if (s.evaluation != IPR_EVAL_COUPLED)
+    return fail(IPR_EARG, "ipr_solve_batched: only the coupled order is supported");
   if (s.tile != 0 && !valid_tile(s.tile))
     return fail(IPR_EARG, "ipr_solve_batched: tile must be 0, 32 or 64");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve_batched: max_iter < 0");

@@ -161,6 +161,25 @@ __global__ __launch_bounds__(NT) void symmetrize_kernel(double* __restrict__ X, 
   }
 }
 
+// Y = X^T (Y must not alias X), 32 x 32 tiles through LDS so that reads and
+// writes are row segments: block (bx, by) reads rows 32 by.. of columns 32 bx..
+// and writes them as rows 32 bx.. of columns 32 by...
+__global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ X, int n,
+                                                        double* __restrict__ Y) {
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = r0 + r, j = c0 + tx;
+    if (i < n && j < n) t[r][tx] = X[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = c0 + r, j = r0 + tx;  // Y[i][j] = X[j][i]
+    if (i < n && j < n) Y[(size_t)i * n + j] = t[tx][r];
+  }
+}
+
 // Y = a0 I + a1 A + a2 G.
 __global__ __launch_bounds__(NT) void lincomb_kernel(const double* __restrict__ A,
                                                       const double* __restrict__ G, int n,
@@ -225,6 +244,13 @@ hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1
 
 hipError_t symmetrize(double* X, int n, hipStream_t stream) {
   hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_for((size_t)n * n)), dim3(NT), 0, stream, X, n);
+  return hipGetLastError();
+}
+
+hipError_t transpose(const double* X, int n, double* Y, hipStream_t stream) {
+  if (X == Y) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(transpose_kernel, dim3(nb, nb), dim3(256), 0, stream, X, n, Y);
   return hipGetLastError();
 }
 

@@ -64,6 +64,8 @@ hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1
 
 // X <- (X + X^T) / 2 in place.
 hipError_t symmetrize(double* X, int n, hipStream_t stream);
+// Y = X^T for n x n row-major X (Y must not alias X).
+hipError_t transpose(const double* X, int n, double* Y, hipStream_t stream);
 
 // Lanczos vector kernels (lanczos.hip)
 hipError_t lz_gemv(const double* A, int n, const double* x, double* y, hipStream_t stream);

@@ -377,6 +377,42 @@ struct Solver {
     return IPR_OK;
   }
 
+  // Literal order of eq. (1): X = C^p A (into Nb[1]) and the partial sums of
+  // (I - X)^2. The iterate is not kept symmetric, so every left operand of a
+  // product (which the kernel reads as L^T) is transposed first; C^T stays in
+  // Mb[0] for the update.
+  int literal_x() {
+    double* T = Mb[0];
+    double* T2 = Nb[0];
+    double* Pb[2] = {Mb[1], X[0]};
+    TRY(transpose(C(), n, T, st));
+    for (int j = 2; j <= p; ++j) {  // C^j = C^{j-1} C
+      Epilogue e;
+      e.D = Pb[j & 1];
+      TRY(prod.f64(j == 2 ? T : T2, C(), 0, e));
+      TRY(transpose(e.D, n, T2, st));
+    }
+    Epilogue e;
+    e.D = Nb[1];
+    e.partial = w.partial;
+    e.pd = 1.0;
+    TRY(prod.f64(p == 1 ? T : T2, A, 0, e));
+    slots = prod.slots(0);
+    return reduce();
+  }
+
+  // C_{k+1} = ((p + 1) C_k - C_k X) / p with X from literal_x().
+  int literal_update() {
+    Epilogue e;
+    e.alpha = -1.0 / p;
+    e.beta = (p + 1.0) / p;
+    e.X = C();
+    e.D = Cb[ci ^ 1];
+    TRY(prod.f64(Mb[0], Nb[1], 0, e));
+    ci ^= 1;
+    return IPR_OK;
+  }
+
   // ||I - C^p A||_F into *tau (host): the symmetric powers C^2 .. C^p as
   // triangle products (when enabled), then one full product C^p A.
   int true_residual(double* tau) {
@@ -401,6 +437,13 @@ struct Solver {
   // reorthogonalisation: an estimate of lambda_min(A) from above. buf holds
   // (steps + 2) n + steps + 2 doubles.
   int lanczos_min(int steps, double* buf, double* theta) {
+    double hi;
+    return lanczos_range(A, steps, buf, theta, &hi);
+  }
+
+  // Smallest and largest Ritz values of `steps` Lanczos steps on the
+  // symmetric matrix S (estimates of its extreme eigenvalues from inside).
+  int lanczos_range(const double* S, int steps, double* buf, double* theta, double* theta_hi) {
     double* Q = buf;
     double* wv = buf + (size_t)(steps + 1) * n;
     double* h = wv + n;
@@ -411,7 +454,7 @@ struct Solver {
     TRY(lz_scale(Q, n, 1.0 / std::sqrt(hs[0]), Q, st));
     std::vector<double> al, be;
     for (int j = 0; j < steps; ++j) {
-      TRY(lz_gemv(A, n, Q + (size_t)j * n, wv, st));
+      TRY(lz_gemv(S, n, Q + (size_t)j * n, wv, st));
       TRY(lz_dots(Q, j + 1, n, wv, h, st));  // h[j] = q_j . A q_j = alpha_j
       if (int rc = read_scalars(h + j, 1, hs, st)) return rc;
       al.push_back(hs[0]);
@@ -427,6 +470,9 @@ struct Solver {
     }
     be.resize(al.size() > 0 ? al.size() - 1 : 0);
     *theta = tridiag_min(al.data(), be.data(), (int)al.size());
+    std::vector<double> neg(al.size());
+    for (size_t i = 0; i < al.size(); ++i) neg[i] = -al[i];
+    *theta_hi = -tridiag_min(neg.data(), be.data(), (int)neg.size());
     return IPR_OK;
   }
 
@@ -517,8 +563,14 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   if (n < 1 || p < 1 || p > 64) return fail(IPR_EARG, "ipr_solve: need n >= 1 and 1 <= p <= 64");
   if (!(tol > 0.0)) return fail(IPR_EARG, "ipr_solve: tol must be > 0");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve: max_iter < 0");
-  if (s.init < IPR_INIT_IDENTITY || s.init > IPR_INIT_LEARNED)
+  if (s.init < IPR_INIT_IDENTITY || s.init > IPR_INIT_USER)
     return fail(IPR_EARG, "ipr_solve: unknown init %d", s.init);
+  if (s.evaluation < IPR_EVAL_COUPLED || s.evaluation > IPR_EVAL_NEWTON_SCHULZ)
+    return fail(IPR_EARG, "ipr_solve: unknown evaluation %d", s.evaluation);
+  if (s.evaluation == IPR_EVAL_NEWTON_SCHULZ && p != 1)
+    return fail(IPR_EARG, "ipr_solve: the Newton-Schulz order is the p = 1 case");
+  if (s.evaluation != IPR_EVAL_COUPLED && s.bulk_dtype != IPR_FP64)
+    return fail(IPR_EARG, "ipr_solve: the literal and Newton-Schulz orders run in FP64 only");
   if (s.bulk_dtype < IPR_FP64 || s.bulk_dtype > IPR_FP8_E4M3)
     return fail(IPR_EARG, "ipr_solve: unknown bulk dtype %d", s.bulk_dtype);
   if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
@@ -675,7 +727,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   // residual is below 1 it bounds both ends, and from a lower end of 1/2 on
   // the steps are unscaled. mu_0 is folded into the start's scale.
   bool dyn = s.dynamic_scaling && init == IPR_INIT_IDENTITY && s.bulk_dtype == IPR_FP64 &&
-             n >= 32;
+             s.evaluation == IPR_EVAL_COUPLED && n >= 32;
   double mod_a = 0.0, mod_b = 1.0, mu_k = 1.0;
   if (dyn) {
     double theta = 0.0;
@@ -693,7 +745,9 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   }
 
   const double root = std::pow(sc, -1.0 / p);
-  if (b[1] == 0.0 && b[2] == 0.0) {
+  if (init == IPR_INIT_USER) {
+    // C_0 is the caller's, already in dC (= C buffer 0); its residual below
+  } else if (b[1] == 0.0 && b[2] == 0.0) {
     // scaled identity c I, c = b0 sc^{-1/p}: M_0 = c^p A elementwise
     const double c = b[0] * root;
     HIP_TRY(init_identity(dA, n, p, c, std::pow(b[0], (double)p) / sc, sv.C(), sv.M(),
@@ -715,7 +769,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
                       stream));
     }
     // M_0 = C_0^p A: products of polynomials in A, symmetric
-    if (int rc = sv.power_chain(sv.C(), dA, sv.M(), sv.Nb[sv.ni], sv.tri)) return rc;
+    if (s.evaluation == IPR_EVAL_COUPLED)
+      if (int rc = sv.power_chain(sv.C(), dA, sv.M(), sv.Nb[sv.ni], sv.tri)) return rc;
   }
   tm.mark(2);
 
@@ -734,6 +789,95 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     sv.slots = n;
     return sv.reduce();
   };
+  const bool literal = s.evaluation == IPR_EVAL_LITERAL;
+  const bool ns_order = s.evaluation == IPR_EVAL_NEWTON_SCHULZ;
+  // Residual of the start for the chosen order: R_0 = I - A C_0 (Newton-Schulz),
+  // M_0 = C_0^p A for a caller's start (coupled; the other starts built M_0),
+  // X_0 = C_0^p A (literal).
+  auto start_residual = [&]() -> int {
+    if (ns_order) return sv.recompute(true);
+    if (literal) return sv.literal_x();
+    if (init == IPR_INIT_USER) return sv.power_chain(sv.C(), dA, sv.M(), sv.Nb[sv.ni], sv.tri);
+    return IPR_OK;
+  };
+  if (int rc = start_residual()) return rc;
+  if (init == IPR_INIT_USER) {
+    // Eq. (2) for the caller's start. ||I - R||_F < 1 (R = C_0^p A, or A C_0
+    // in Newton-Schulz order) bounds the spectrum inside (0, 2) outright.
+    // Otherwise, for the coupled and literal orders, a Lanczos estimate of
+    // the extreme eigenvalues of the symmetric C_0^p A must lie in (0, 1.9)
+    // (an estimate from inside the spectrum, hence the margin).
+    double r0;
+    if (int rc = read_scalars(sv.rho_dev(), 1, &r0, stream)) return rc;
+    bool ok = r0 < 1.0;
+    double lo = 1.0 - r0, hi = 1.0 + r0;
+    if (!ok && !ns_order && std::isfinite(r0) && n >= 16) {  // (the Lanczos basis fits w.m[0])
+      const double* M0 = literal ? sv.Nb[1] : sv.M();
+      if (int rc = sv.lanczos_range(M0, std::max(1, std::min(24, n - 8)), w.m[0], &lo, &hi))
+        return rc;
+      ok = lo > 0.0 && hi < 1.9;
+    }
+    res.init_bound = hi;
+    res.init_scale = 0.0;
+    for (double& v : res.poly_used) v = 0.0;
+    if (!ok) {
+      if (!s.guard_fallback)
+        return fail(IPR_EGUARD, "ipr_solve: the caller's start has residual %g >= 1", r0);
+      init = IPR_INIT_IDENTITY;
+      if (int rc = restart_identity()) return rc;
+      res.init_bound = 1.0;
+      res.init_scale = sigma;
+      res.poly_used[0] = 1.0;
+      if (ns_order || literal)
+        if (int rc = start_residual()) return rc;
+    }
+  }
+  if (literal) {
+    // Eq. (1) as printed. X_k = C_k^p A is formed from C_k and A, so its
+    // residual is the true one and no separate check is needed.
+    double best = std::numeric_limits<double>::infinity();
+    int stale = 0;
+    tm.mark(3);
+    for (k = 0;; ++k) {
+      if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
+      res.residual_proxy = rho;
+      res.residual_true = rho;
+      if (!std::isfinite(rho) || rho > 1e6) {
+        status = IPR_EDIVERGED;
+        break;
+      }
+      if (rho < tol) {
+        status = IPR_OK;
+        break;
+      }
+      if (rho < 1.0) {
+        if (rho < s.stall_ratio * best) {
+          best = rho;
+          stale = 0;
+        } else if (++stale >= 3) {
+          status = IPR_EFLOOR;
+          break;
+        }
+      }
+      if (k >= s.max_iter) break;
+      if (int rc = sv.literal_update()) return rc;
+      if (int rc = sv.literal_x()) return rc;
+    }
+    tm.mark(4);
+    res.iters_fp64 = k;
+    if (sv.C() != dC) HIP_TRY(copy(sv.C(), nn, dC, stream));
+    tm.mark(5);
+    HIP_TRY(hipStreamSynchronize(stream));
+    res.ms_norms = tm.ms(0, 1);
+    res.ms_init = tm.ms(1, 2);
+    res.ms_refine = tm.ms(3, 4);
+    res.ms_verify = tm.ms(4, 5);
+    res.status = status;
+    res.gemms = sv.prod.gemms;
+    sv.prod.totals(0, &res.gemm_launches, &res.ms_gemm, &res.gemm_flops);
+    if (out) *out = res;
+    return status;
+  }
   if (lowp) {
     sv.prod.lowp_dtype = s.bulk_dtype;
     if (p == 1)  // Newton-Schulz bulk: R_0 = I - A C_0
@@ -770,8 +914,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     }
   }
   tm.mark(3);
-  // Newton-Schulz order for p = 1 once a low-precision phase has run
-  bool ns = lowp && p == 1 && !lp_restart;
+  // Newton-Schulz order for p = 1 once a low-precision phase has run, or on request
+  bool ns = (lowp && p == 1 && !lp_restart) || ns_order;
   double best = std::numeric_limits<double>::infinity();
   int stale = 0, failed_verify = 0, verified_at = -1;
   bool short_failed = false;

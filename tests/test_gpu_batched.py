@@ -160,6 +160,11 @@ def test_batched_argument_errors(ipr):
     with pytest.raises(ipr.IprError):
         ipr.ipr_solve_batched(dev(buf), offs, [4], [2], 1e-10,
                               schedule=ipr.ipr_schedule_default(tile=48))
+    for kw in (dict(evaluation=ipr.IPR_EVAL_LITERAL), dict(init=ipr.IPR_INIT_USER)):
+        with pytest.raises(ipr.IprError) as ei:
+            ipr.ipr_solve_batched(dev(buf), offs, [4], [1], 1e-10,
+                                  schedule=ipr.ipr_schedule_default(**kw))
+        assert ei.value.code == ipr.IPR_EARG
 
 
 def test_tuner_fills_the_table(ipr):

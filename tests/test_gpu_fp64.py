@@ -96,6 +96,102 @@ def test_cfg1_spd256_p2_golden_count(ipr):
     assert it.rel_fro(c, ref.c) <= 1e-10
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_literal_order_matches_oracle(ipr, p):
+    # eq. (1) as printed, C_{k+1} = ((p+1) C_k - C_k (C_k^p A)) / p without
+    # symmetrisation: at kappa = 10 it converges with the oracle's count; at
+    # kappa = 1e3 rounding errors that do not commute with A grow and neither
+    # the oracle nor the GPU reaches the root (the reason for the coupled order)
+    say("literal p", p)
+    a, _, _ = w.spd_log_spectrum(96, 10.0, seed=50 + p)
+    ref = it.solve(a, p, 1e-10, evaluation="literal")
+    c, r = _solve(ipr, a, p, 1e-10, evaluation=ipr.IPR_EVAL_LITERAL)
+    assert ref.status == it.OK and r.status == ipr.IPR_OK, r.as_dict()
+    assert abs(r.iters_fp64 - ref.iters) <= 1
+    assert r.residual_true < 1e-10
+    assert r.gemms == (p + 1) * r.iters_fp64 + p
+    assert it.rel_fro(c, ref.c) <= 1e-10 and it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    a, _, _ = w.spd_log_spectrum(96, 1e3, seed=50 + p)
+    ref = it.solve(a, p, 1e-10, evaluation="literal")
+    _, r = _solve(ipr, a, p, 1e-10, evaluation=ipr.IPR_EVAL_LITERAL)
+    assert ref.status != it.OK and r.status in (ipr.IPR_EDIVERGED, ipr.IPR_EFLOOR)
+
+
+def test_newton_schulz_order(ipr):
+    a, _, _ = w.spd_log_spectrum(200, 1e3, seed=61)
+    ref = it.solve(a, 1, 1e-10, evaluation="newton_schulz")
+    c, r = _solve(ipr, a, 1, 1e-10, evaluation=ipr.IPR_EVAL_NEWTON_SCHULZ)
+    assert r.status == ipr.IPR_OK and ref.status == it.OK
+    assert abs(r.iters_fp64 - ref.iters) <= 1
+    assert r.residual_true < 1e-10
+    assert it.rel_fro(c, np.linalg.inv(a)) <= 1e-10
+    assert np.array_equal(c, c.T)
+    with pytest.raises(ipr.IprError) as ei:
+        _solve(ipr, a, 2, 1e-10, evaluation=ipr.IPR_EVAL_NEWTON_SCHULZ)
+    assert ei.value.code == ipr.IPR_EARG
+    with pytest.raises(ipr.IprError) as ei:
+        _solve(ipr, a, 1, 1e-10, evaluation=ipr.IPR_EVAL_LITERAL, bulk_dtype=ipr.IPR_BF16)
+    assert ei.value.code == ipr.IPR_EARG
+
+
+def _solve_from(ipr, a, c0, p, tol, **sched):
+    s = ipr.ipr_schedule_default(init=ipr.IPR_INIT_USER, **sched)
+    C, res = ipr.ipr_solve(dev(a), p, tol, schedule=s, out=dev(c0))
+    return host(C), res
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_user_start(ipr, p):
+    n = 160
+    a, lam, q = w.spd_log_spectrum(n, 1e3, seed=80 + p)
+    # the scaled identity given as C_0: the default start's iterates
+    c0 = it.start_identity(a, p)
+    c, r = _solve_from(ipr, a, c0, p, 1e-10)
+    _, r0 = _solve(ipr, a, p, 1e-10)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 0
+    assert abs(r.iters_fp64 - r0.iters_fp64) <= 1
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    # a polynomial in A given as C_0: the POLY start's iterates. (A C_0 that
+    # is not a function of A to rounding, e.g. an earlier iterate, stalls in
+    # the coupled order: M_0 = C_0^p A then carries the non-commuting error.)
+    poly = (0.7, 0.3, 0.0)   # q(x)^p x <= 1 on (0, 1]
+    c0 = it.start_poly(a, p, poly)
+    c, r = _solve_from(ipr, a, c0, p, 1e-10)
+    cp, rp = _solve(ipr, a, p, 1e-10, init=ipr.IPR_INIT_POLY, poly=poly)
+    assert r.status == ipr.IPR_OK and rp.status == ipr.IPR_OK and r.fallback_used == 0
+    assert abs(r.iters_fp64 - rp.iters_fp64) <= 1
+    # the Lanczos estimate of the top of the spectrum of C_0^p A (below 1 here)
+    assert 0.0 < r.init_bound <= 1.0 + 1e-9 and r.init_scale == 0.0
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    # a start outside eq. (2): the scaled identity instead, or an error
+    c0 = 10.0 * np.eye(n)
+    c, r = _solve_from(ipr, a, c0, p, 1e-10)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 1
+    assert r.iters_fp64 == r0.iters_fp64
+    with pytest.raises(ipr.IprError) as ei:
+        _solve_from(ipr, a, c0, p, 1e-10, guard_fallback=0)
+    assert ei.value.code == ipr.IPR_EGUARD
+
+
+def test_user_start_newton_schulz_self_corrects(ipr):
+    # p = 1 in Newton-Schulz order from an inverse with a perturbation that
+    # does not commute with A: the error squares every step
+    n = 200
+    a, _, _ = w.spd_log_spectrum(n, 1e3, seed=91)
+    rng = np.random.default_rng(5)
+    e = rng.standard_normal((n, n))
+    e = (e + e.T) / 2
+    ainv = np.linalg.inv(a)
+    c0 = ainv + 1e-4 * ainv @ e @ ainv / np.linalg.norm(e, 2)   # ||I - A C_0||_F ~ 0.2
+    c0 = 0.5 * (c0 + c0.T)
+    ref = it.solve(a, 1, 1e-10, init=c0, evaluation="newton_schulz")
+    c, r = _solve_from(ipr, a, c0, 1, 1e-10, evaluation=ipr.IPR_EVAL_NEWTON_SCHULZ)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 0 and ref.status == it.OK
+    assert 0.1 < r.init_bound - 1.0 < 0.5
+    assert abs(r.iters_fp64 - ref.iters) <= 1 and r.iters_fp64 <= 4
+    assert it.rel_fro(c, ainv) <= 1e-10
+
+
 @pytest.mark.parametrize("p,kappa,tol", [(1, 10.0, 1e-8), (2, 100.0, 1e-10),
                                          (3, 10.0, 1e-10), (2, 1e4, 1e-10)])
 def test_last_step_without_m_update(ipr, p, kappa, tol):
