@@ -128,6 +128,9 @@ typedef struct {
   double ms_lp_gemm;     /* (matrix-core kernel only; the rounding of operands is not included) */
   double lp_gemm_flops;
   double lmin_est;       /* dynamic_scaling: the Lanczos estimate of lambda_min(A) (0 otherwise) */
+  int reest_iter;        /* dynamic_scaling: the step before which lambda_min(M_k) was estimated
+                            again (once its bound reached 0.03; 0 if not) */
+  double lmin_reest;     /* that estimate (0 if none) */
 } ipr_result;
 
 #define IPR_MLP_NIN 16

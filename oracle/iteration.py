@@ -219,7 +219,9 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
     (C_0 = (s / mu_0)^{-1/p} I); step k uses N = ((p + 1) I - mu_k M)/p,
     C <- mu_k^{1/p} C N, M <- N^p mu_k M, the bounds follow step_bounds, and
     mu_{k+1} = choose_mu of the new bounds; whenever rho = ||I - M_k||_F < 1,
-    the bounds are narrowed to [1 - rho, 1 + rho].
+    the bounds are narrowed to [1 - rho, 1 + rho]. dynamic=(s, theta, (j, t)):
+    in addition, before step j (after its convergence test) the lower bound
+    becomes min(t, hi), t an estimate of lambda_min(M_j) (an input, like theta).
 
     The returned iteration count is the number of updates applied. Status:
     OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
@@ -239,7 +241,8 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
     if dynamic is not None:
         if evaluation != "coupled":
             raise ValueError("the scaled iteration is a coupled form")
-        s, theta = dynamic
+        s, theta = dynamic[0], dynamic[1]
+        reest = dynamic[2] if len(dynamic) > 2 else None
         lo, hi = min(theta / s, 1.0), 1.0
         mu0 = choose_mu(lo, hi, p)
         c = (s / mu0) ** (-1.0 / p) * np.eye(n)
@@ -278,6 +281,8 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
         if k == max_iter:
             break
         if evaluation == "coupled" and dynamic is not None:
+            if reest is not None and k == reest[0]:
+                lo = min(reest[1], hi)
             nmat = ((p + 1) * eye - mu * m) / p
             c = sym(mu ** (1.0 / p) * (c @ nmat))
             m = mu * m

@@ -40,7 +40,8 @@ class IprResult(ct.Structure):
                 ("ms_verify", ct.c_double), ("gemm_launches", ct.c_int), ("ms_gemm", ct.c_double),
                 ("gemm_flops", ct.c_double), ("lp_gemm_launches", ct.c_int),
                 ("ms_lp_gemm", ct.c_double), ("lp_gemm_flops", ct.c_double),
-                ("lmin_est", ct.c_double)]
+                ("lmin_est", ct.c_double), ("reest_iter", ct.c_int),
+                ("lmin_reest", ct.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -106,6 +106,9 @@ using namespace ipr;
 namespace {
 
 constexpr int NMAT = 7;     // float64 n x n work matrices
+// Lower end of the scaled iteration's spectrum bound at which lambda_min(M_k)
+// is estimated again (dynamic scaling)
+constexpr double kReestimateAt = 0.03;
 constexpr int NLP = 6;      // quantized operand slots (low-precision phase)
 
 struct Work {
@@ -918,7 +921,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   bool ns = (lowp && p == 1 && !lp_restart) || ns_order;
   double best = std::numeric_limits<double>::infinity();
   int stale = 0, failed_verify = 0, verified_at = -1;
-  bool short_failed = false;
+  bool short_failed = false, reestimated = false;
   double last_tau = std::numeric_limits<double>::infinity();
   double prev = std::numeric_limits<double>::infinity();
   const int kmax = s.max_iter - res.iters_bulk;
@@ -983,6 +986,23 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       break;
     }
     if (k >= kmax) break;
+    if (dyn && !reestimated && k >= 1 && mod_a >= kReestimateAt) {
+      // Lanczos on A converges slowly to lambda_min when the small
+      // eigenvalues are dense (an overestimate by 7x at kappa = 1e4 after 24
+      // steps), and then every factor is smaller than it could be. Once the
+      // scaled steps have lifted the lower end of M_k to kReestimateAt, M_k is
+      // well conditioned and the same number of steps on it estimates its
+      // lower end closely; the bound is replaced by that estimate, once.
+      double th, hi;
+      if (int rc = sv.lanczos_range(sv.M(), std::min(24, n - 8), sv.Cb[sv.ci ^ 1], &th, &hi))
+        return rc;
+      reestimated = true;
+      if (th > 0.0 && std::isfinite(th)) {
+        mod_a = std::min(th, mod_b);
+        res.reest_iter = k;
+        res.lmin_reest = th;
+      }
+    }
     if (dyn) {
       double na, nb;
       step_bounds(mod_a, mod_b, mu_k, p, &na, &nb);

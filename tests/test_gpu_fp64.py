@@ -246,7 +246,11 @@ def test_dynamic_scaling(ipr, p, squarings):
     assert lam.min() - 1e-12 * lam.max() <= r.lmin_est <= lam.max() * (1 + 1e-12)
     assert r.iters_fp64 < r0.iters_fp64
     assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
-    ref = it.solve(a, p, 1e-10, dynamic=(r.init_scale, r.lmin_est))
+    dyn = (r.init_scale, r.lmin_est)
+    if r.reest_iter > 0:   # the lower end estimated again on M_k (an input to the oracle)
+        assert 0.0 < r.lmin_reest <= 1.0 + 1e-12
+        dyn = dyn + ((r.reest_iter, r.lmin_reest),)
+    ref = it.solve(a, p, 1e-10, dynamic=dyn)
     assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1
     # A = c I: Lanczos stops after one step at c, and nothing is scaled
     C, r = ipr.ipr_solve(dev(2.5 * np.eye(64)), p, 1e-10,

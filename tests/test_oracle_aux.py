@@ -178,6 +178,28 @@ def test_scaled_iteration_reaches_the_root_in_fewer_steps():
             assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
 
 
+def test_reestimated_lower_end_recovers_the_exact_count():
+    # theta 7x too large (what a short Lanczos run on A gives for a dense low
+    # spectrum) costs iterations; replacing the lower bound before step j by
+    # the exact lambda_min(M_j) brings the count back to that of the exact
+    # theta, for any early j, and the iteration still reaches the root
+    import workloads as w
+    from oracle import iteration as it
+    for p in (1, 2, 3):
+        a, lam, _ = w.spd_log_spectrum(160, 1e4, seed=70 + p)
+        s, _ = it.power_scale(a, p, 6, scaled_steps=True)
+        th = 7.0 * lam.min()
+        base = it.solve(a, p, 1e-10, dynamic=(s, th))
+        exact = it.solve(a, p, 1e-10, dynamic=(s, lam.min()))
+        assert exact.iters < base.iters
+        for j in (1, 3):
+            cj = it.solve(a, p, 1e-30, max_iter=j, dynamic=(s, th)).c
+            t = np.linalg.eigvalsh(it.matpow(cj, p) @ a).min()
+            r = it.solve(a, p, 1e-10, dynamic=(s, th, (j, t)))
+            assert r.status == it.OK and r.iters == exact.iters
+            assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
+
+
 def test_scaled_iteration_keeps_the_p1_floor():
     # p = 1 at kappa = 6e4: with the scaled top capped at 1 + 1/sqrt(2) the
     # scaled iteration reaches 1e-10 like the plain one (a cap of 1.98 left
