@@ -257,6 +257,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
       r.init_bound = 1.0;
       r.init_scale = res[i].init_scale;
       r.lmin_est = res[i].lmin_est;
+      r.reest_iter = res[i].reest_iter;
+      r.lmin_reest = res[i].lmin_reest;
       r.poly_used[0] = 1.0;
     }
     if (res[i].status != IPR_OK && status == IPR_OK) status = res[i].status;

@@ -19,6 +19,8 @@ struct BatchResult {
   int status, iters_bulk, iters_fp64, fallback_used;
   double residual_proxy, residual_true, norm1, norminf;
   double init_scale, lmin_est;
+  double lmin_reest;  // lower end of M_k estimated again (scaled steps), before step reest_iter
+  int reest_iter, pad;
 };
 
 struct BatchArgs {

@@ -293,6 +293,76 @@ struct Bufs {
   double* X[2];
 };
 
+// Smallest Ritz value of LZ_STEPS Lanczos steps on the symmetric n x n
+// matrix S (three-term recurrence with one reorthogonalisation against q_j;
+// vec holds 3 n doubles), in every thread: an estimate of lambda_min(S) from
+// above. Called by the whole workgroup.
+__device__ __noinline__ double lanczos_min_wg(const double* S, int n, double* vec, Smem& sm) {
+  const int tid = threadIdx.x;
+  double* qp = vec;          // q_{j-1}
+  double* qc = vec + n;      // q_j
+  double* wv = vec + 2 * (size_t)n;
+  double nrm = 0.0;
+  for (int t = tid; t < n; t += NT) {
+    uint64_t z = (uint64_t)t + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double v = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+    qc[t] = v;
+    qp[t] = 0.0;
+    nrm += v * v;
+  }
+  nrm = sqrt(block_sum(nrm, sm));
+  for (int t = tid; t < n; t += NT) qc[t] /= nrm;
+  double beta = 0.0;
+  int m = 0;
+  for (int j = 0; j < LZ_STEPS; ++j) {
+    __syncthreads();
+    for (int i = tid >> 6; i < n; i += NT / 64) {  // w = S q_j, one wave per row
+      double rs = 0.0;
+      for (int c2 = tid & 63; c2 < n; c2 += 64) rs += S[(size_t)i * n + c2] * qc[c2];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
+      if ((tid & 63) == 0) wv[i] = rs;
+    }
+    __syncthreads();
+    double pa = 0.0;
+    for (int t = tid; t < n; t += NT) pa += wv[t] * qc[t];
+    const double alpha = block_sum(pa, sm);
+    double pr = 0.0;
+    for (int t = tid; t < n; t += NT) {
+      const double v = wv[t] - alpha * qc[t] - beta * qp[t];
+      wv[t] = v;
+      pr += v * qc[t];
+    }
+    // one reorthogonalisation step against q_j
+    const double r = block_sum(pr, sm);
+    double pb2 = 0.0;
+    for (int t = tid; t < n; t += NT) {
+      const double v = wv[t] - r * qc[t];
+      wv[t] = v;
+      pb2 += v * v;
+    }
+    const double bnew = sqrt(block_sum(pb2, sm));
+    if (tid == 0) sm.al[j] = alpha + r;
+    m = j + 1;
+    if (j + 1 == LZ_STEPS || !(bnew > 1e-10 * fabs(alpha))) break;
+    if (tid == 0) sm.be[j] = bnew;
+    for (int t = tid; t < n; t += NT) {
+      qp[t] = qc[t];
+      qc[t] = wv[t] / bnew;
+    }
+    beta = bnew;
+  }
+  __syncthreads();
+  if (tid == 0) sm.bcast[0] = tridiag_min(sm.al, sm.be, m);
+  __syncthreads();
+  const double theta = sm.bcast[0];
+  __syncthreads();
+  return theta;
+}
+
 __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs args) {
   __shared__ Smem sm;
   __shared__ __attribute__((aligned(16))) char qraw[QMAX * sizeof(ProdDesc)];
@@ -320,6 +390,8 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     res.status = 2;  // EMAXITER unless set below
     res.iters_bulk = res.iters_fp64 = 0;
     res.fallback_used = 0;
+    res.reest_iter = 0;
+    res.lmin_reest = 0.0;
     res.residual_true = -1.0;
     res.residual_proxy = 0.0;
 
@@ -394,69 +466,7 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     double ma = 0.0, mb = 1.0, mu_k = 1.0;
     bool dyn = false;
     if (dyn0) {
-      double* qp = b.M[1];       // q_{j-1}
-      double* qc = b.M[1] + n;   // q_j
-      double* wv = b.M[1] + 2 * (size_t)n;
-      double nrm = 0.0;
-      for (int t = tid; t < n; t += NT) {
-        uint64_t z = (uint64_t)t + 0x9E3779B97F4A7C15ull;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        z ^= z >> 31;
-        const double v = (double)(z >> 11) * 0x1.0p-52 - 1.0;
-        qc[t] = v;
-        qp[t] = 0.0;
-        nrm += v * v;
-      }
-      nrm = sqrt(block_sum(nrm, sm));
-      for (int t = tid; t < n; t += NT) qc[t] /= nrm;
-      double beta = 0.0;
-      int m = 0;
-      for (int j = 0; j < LZ_STEPS; ++j) {
-        __syncthreads();
-        for (int i = tid >> 6; i < n; i += NT / 64) {  // w = A q_j, one wave per row
-          double rs = 0.0;
-          for (int c2 = tid & 63; c2 < n; c2 += 64) rs += b.A[(size_t)i * n + c2] * qc[c2];
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
-          if ((tid & 63) == 0) wv[i] = rs;
-        }
-        __syncthreads();
-        double pa = 0.0;
-        for (int t = tid; t < n; t += NT) pa += wv[t] * qc[t];
-        const double alpha = block_sum(pa, sm);
-        double pb = 0.0, pr = 0.0;
-        for (int t = tid; t < n; t += NT) {
-          const double v = wv[t] - alpha * qc[t] - beta * qp[t];
-          wv[t] = v;
-          pb += v * v;
-          pr += v * qc[t];
-        }
-        // one reorthogonalisation step against q_j
-        const double r = block_sum(pr, sm);
-        double pb2 = 0.0;
-        for (int t = tid; t < n; t += NT) {
-          const double v = wv[t] - r * qc[t];
-          wv[t] = v;
-          pb2 += v * v;
-        }
-        (void)pb;
-        const double bnew = sqrt(block_sum(pb2, sm));
-        if (tid == 0) sm.al[j] = alpha + r;
-        m = j + 1;
-        if (j + 1 == LZ_STEPS || !(bnew > 1e-10 * fabs(alpha))) break;
-        if (tid == 0) sm.be[j] = bnew;
-        for (int t = tid; t < n; t += NT) {
-          qp[t] = qc[t];
-          qc[t] = wv[t] / bnew;
-        }
-        beta = bnew;
-      }
-      __syncthreads();
-      if (tid == 0) sm.bcast[0] = tridiag_min(sm.al, sm.be, m);
-      __syncthreads();
-      const double theta = sm.bcast[0];
-      __syncthreads();
+      const double theta = lanczos_min_wg(b.A, n, b.M[1], sm);
       res.lmin_est = theta;
       if (theta > 0.0 && isfinite(theta)) {
         dyn = true;
@@ -568,6 +578,7 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     // ---- FP64 iterations
     double best = 1e300, last_tau = 1e300;
     int stale = 0, failed = 0, k = 0;
+    bool reestimated = false;
     const int kmax = args.max_iter - res.iters_bulk;
     for (k = 0;; ++k) {
       res.residual_proxy = rho;
@@ -636,6 +647,17 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
       // C' = C N; M' = N (N (... (N M))) with N' = ((p+1) I - M') / p; with
       // scaled steps C' = mu^{1/p} C N, M' = N^p mu M, N' = ((p+1) I - mu' M')/p
       double mu_n = 1.0;
+      if (dyn && !reestimated && k >= 1 && ma >= 0.03) {
+        // the lower end estimated again on the now well-conditioned M_k (as
+        // the single solve does); C[ci ^ 1] is free until this step writes it
+        reestimated = true;
+        const double th = lanczos_min_wg(b.M[mi], n, b.C[ci ^ 1], sm);
+        if (th > 0.0 && isfinite(th)) {
+          ma = fmin(th, mb);
+          res.reest_iter = k;
+          res.lmin_reest = th;
+        }
+      }
       if (dyn) {
         double na, nb;
         step_bounds(ma, mb, mu_k, p, &na, &nb);

@@ -194,7 +194,10 @@ def test_batched_scaled_steps(ipr):
         assert lam.max() <= r.init_scale * (1 + 1e-12)
         if n >= 32:
             assert lam.min() - 1e-12 * lam.max() <= r.lmin_est <= lam.max() * (1 + 1e-12)
-            ref = it.solve(a, p, 1e-10, dynamic=(r.init_scale, r.lmin_est))
+            dyn = (r.init_scale, r.lmin_est)
+            if r.reest_iter > 0:
+                dyn = dyn + ((r.reest_iter, r.lmin_reest),)
+            ref = it.solve(a, p, 1e-10, dynamic=dyn)
             assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1, (n, p)
         else:
             assert r.lmin_est == 0.0
