@@ -148,16 +148,29 @@ __global__ __launch_bounds__(NT) void copy_kernel(const double* __restrict__ X, 
 }
 
 // X <- (X + X^T) / 2 in place: thread t owns the pair (i, j), i < j.
-__global__ __launch_bounds__(NT) void symmetrize_kernel(double* __restrict__ X, int n) {
-  const size_t total = (size_t)n * n;
-  for (size_t t = (size_t)blockIdx.x * NT + threadIdx.x; t < total;
-       t += (size_t)gridDim.x * NT) {
-    const size_t i = t / n, j = t - i * n;
-    if (i < j) {
-      const double v = 0.5 * (X[i * n + j] + X[j * n + i]);
-      X[i * n + j] = v;
-      X[j * n + i] = v;
-    }
+// X <- (X + X^T) / 2 in place. Block (bx, by) with bx >= by owns the tile
+// pair (by, bx) / (bx, by): both 32 x 32 tiles are read as row segments into
+// LDS, averaged, and written back as row segments (the diagonal tile pairs
+// with itself). Blocks with bx < by have nothing to do.
+__global__ __launch_bounds__(256) void symmetrize_kernel(double* __restrict__ X, int n) {
+  __shared__ double u[32][33], v[32][33];
+  const int bx = blockIdx.x, by = blockIdx.y;
+  if (bx < by) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int r0 = by * 32, c0 = bx * 32;  // tile U = X[r0.., c0..], tile V = X[c0.., r0..]
+  for (int r = ty; r < 32; r += 8) {
+    const int i = r0 + r, j = c0 + tx;
+    if (i < n && j < n) u[r][tx] = X[(size_t)i * n + j];
+    const int i2 = c0 + r, j2 = r0 + tx;
+    if (i2 < n && j2 < n) v[r][tx] = X[(size_t)i2 * n + j2];
+  }
+  __syncthreads();
+  // U[r][c] pairs with V[c][r]
+  for (int r = ty; r < 32; r += 8) {
+    const int i = r0 + r, j = c0 + tx;
+    if (i < n && j < n) X[(size_t)i * n + j] = 0.5 * (u[r][tx] + v[tx][r]);
+    const int i2 = c0 + r, j2 = r0 + tx;
+    if (i2 < n && j2 < n) X[(size_t)i2 * n + j2] = 0.5 * (v[r][tx] + u[tx][r]);
   }
 }
 
@@ -243,7 +256,8 @@ hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1
 }
 
 hipError_t symmetrize(double* X, int n, hipStream_t stream) {
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(grid_for((size_t)n * n)), dim3(NT), 0, stream, X, n);
+  const unsigned nb = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(nb, nb), dim3(256), 0, stream, X, n);
   return hipGetLastError();
 }
 
