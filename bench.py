@@ -130,6 +130,32 @@ def solve_record(ipr, r, seconds, dtype_name=None):
     return d
 
 
+def householder_kappa1e2_runs(ipr, torch, w, dev, tol, p=2, n=16384):
+    """The n = 16384 Householder matrix at kappa = 1e2 (the other condition
+    number of that workload): the headline schedule, the plain iteration, and
+    fp16 / fp8 bulk phases with FP64 refinement."""
+    a, _ = w.householder_spd(n, 1e2, seed=0)
+    A = torch.from_numpy(a).to(dev)
+    del a
+    C = torch.empty_like(A)
+    out = {"workload": f"householder_spd n={n} p={p} kappa=100 seed=0", "tol": tol}
+    for name, kw, dtn in (
+            ("fp64_power_scale_scaled_steps", dict(scale_squarings=6, dynamic_scaling=1), None),
+            ("fp64_identity_norm_scale", {}, None),
+            ("fp16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP16), "fp16"),
+            ("fp8_e4m3_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP8_E4M3), "fp8_e4m3")):
+        s = ipr.ipr_schedule_default(timing=1, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C)
+        torch.cuda.synchronize()
+        out[name] = solve_record(ipr, r, time.perf_counter() - t, dtn)
+        log(f"kappa 1e2 {name}", json.dumps(out[name]))
+    del A, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def kernel_matrix_runs(ipr, torch, w, dev, tol):
     """The Gaussian-kernel Gram matrix, n = 4096: plain FP64 against a bf16
     bulk phase with FP64 refinement, p = 1, 2, 3."""
@@ -365,6 +391,8 @@ def main():
     out["comparators"] = comps
 
     if not args.no_extra:
+        out["householder_16384_kappa1e2"] = householder_kappa1e2_runs(ipr, torch, w, dev, tol,
+                                                                      p=p, n=n)
         out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
         out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
 
