@@ -151,7 +151,7 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
 /* A^{-1/p} of one SPD matrix (Section II, eqs. (1)-(3)).
  *   dA    device, n x n float64, symmetric (read only)
  *   dC    device, n x n float64: receives A^{-1/p} (exactly symmetric, except with the
- *         LITERAL order); with IPR_INIT_USER it holds C_0 on entry
+ *         LITERAL order); with IPR_INIT_USER it holds C_0 on entry; must not alias dA
  *   tol   stop when ||I - C^p A||_F < tol (> 0)
  *   s     schedule (NULL = defaults)
  *   out   host, receives the result record (may be NULL)

@@ -563,6 +563,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   std::memset(&res, 0, sizeof res);
   res.residual_true = std::numeric_limits<double>::quiet_NaN();
   if (!dA || !dC || !dWork) return fail(IPR_EARG, "ipr_solve: null pointer");
+  if ((const void*)dA == (const void*)dC) return fail(IPR_EARG, "ipr_solve: dC must not alias dA");
   if (n < 1 || p < 1 || p > 64) return fail(IPR_EARG, "ipr_solve: need n >= 1 and 1 <= p <= 64");
   if (!(tol > 0.0)) return fail(IPR_EARG, "ipr_solve: tol must be > 0");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve: max_iter < 0");

@@ -317,6 +317,13 @@ def test_argument_errors(ipr):
     small = torch.empty(1024, dtype=torch.uint8, device="cuda")
     with pytest.raises(ipr.IprError):
         ipr.ipr_solve(a, 2, 1e-10, workspace=small)
+    with pytest.raises(ipr.IprError) as ei:   # the output may not overwrite the input
+        ipr.ipr_solve(a, 2, 1e-10, out=a)
+    assert ei.value.code == ipr.IPR_EARG
+    for bad in (dict(evaluation=3), dict(init=5)):
+        with pytest.raises(ipr.IprError) as ei:
+            ipr.ipr_solve(a, 2, 1e-10, schedule=ipr.ipr_schedule_default(**bad))
+        assert ei.value.code == ipr.IPR_EARG
 
 
 def test_maxiter_and_divergence_status(ipr):
