@@ -153,6 +153,32 @@ def test_batched_recipe_sample(ipr):
     say("recipe sample: OK", n_ok, "of", len(items))
 
 
+def test_batched_full_recipe_2000(ipr):
+    # the benchmarked batch itself (2000 items, default tile table, one
+    # graph-captured launch per schedule): every item against the definition,
+    # for the plain schedule and for the power scale with scaled steps
+    items = w.batch_recipe(2000)
+    mats = [w.batch_matrix(n, kappa, seed)[0] for (n, p, kappa, seed) in items]
+    ns = [n for (n, _, _, _) in items]
+    ps = [p for (_, p, _, _) in items]
+    roots = [it.eig_root(a, p) for a, p in zip(mats, ps)]
+    buf, offs = _pack(mats)
+    A = dev(buf)
+    for kw in ({}, dict(scale_squarings=6, dynamic_scaling=1)):
+        C, res = ipr.ipr_solve_batched(A, offs, ns, ps, 1e-10,
+                                       schedule=ipr.ipr_schedule_default(**kw))
+        cs = _unpack(host(C), offs, ns)
+        n_ok = 0
+        worst = 0.0
+        for (n, p, kappa, seed), c, root, r in zip(items, cs, roots, res):
+            err = it.rel_fro(c, root)
+            worst = max(worst, err)
+            assert err <= 1e-10, (n, p, kappa, seed, err, r.as_dict())
+            assert r.status == ipr.IPR_OK or (r.status == ipr.IPR_EFLOOR and kappa > 2e4)
+            n_ok += r.status == ipr.IPR_OK
+        say("full batch", kw, "OK", n_ok, "of", len(items), "worst rel err", worst)
+
+
 def test_batched_argument_errors(ipr):
     buf, offs = _pack([np.eye(4)])
     with pytest.raises(ipr.IprError):
