@@ -156,7 +156,8 @@ def test_batched_recipe_sample(ipr):
 def test_batched_full_recipe_2000(ipr):
     # the benchmarked batch itself (2000 items, default tile table, one
     # graph-captured launch per schedule): every item against the definition,
-    # for the plain schedule and for the power scale with scaled steps
+    # for the plain schedule, the power scale with scaled steps, and a bf16
+    # bulk phase (p = 1 items) before FP64
     items = w.batch_recipe(2000)
     mats = [w.batch_matrix(n, kappa, seed)[0] for (n, p, kappa, seed) in items]
     ns = [n for (n, _, _, _) in items]
@@ -164,7 +165,7 @@ def test_batched_full_recipe_2000(ipr):
     roots = [it.eig_root(a, p) for a, p in zip(mats, ps)]
     buf, offs = _pack(mats)
     A = dev(buf)
-    for kw in ({}, dict(scale_squarings=6, dynamic_scaling=1)):
+    for kw in ({}, dict(scale_squarings=6, dynamic_scaling=1), dict(bulk_dtype=ipr.IPR_BF16)):
         C, res = ipr.ipr_solve_batched(A, offs, ns, ps, 1e-10,
                                        schedule=ipr.ipr_schedule_default(**kw))
         cs = _unpack(host(C), offs, ns)
