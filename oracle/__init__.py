@@ -24,6 +24,8 @@ Parity pins (tests marked "not gpu" check each of these):
   * features           - against hand-computed values on small matrices.
   * guard              - against dense sampling and the closed forms of the
                          paper's eq. (3) start.
+  * int8-slice product - against exact integer and rational arithmetic
+                         (brute force on tiny inputs) and its error bound.
 Parity unpinned: none of the functions above lacks a pin. The accuracy the
 low-precision bulk phase reaches end to end has no value in the paper to
 compare with (its figures are not available); it is checked against this
