@@ -205,6 +205,26 @@ int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dty
                   void* dWork, size_t work_bytes, hipStream_t stream);
 size_t ipr_gemm_lowp_workspace(int n);
 
+/* FP64-accurate product D = L^T R on the int8 matrix cores: the low-precision
+ * units Section III-B asks for, at the accuracy the iteration needs (eq. (1)
+ * for p >= 2 floors unless its products are FP64-accurate). Error-free
+ * splitting into 8-bit digits (Ozaki, Ogita, Oishi and Rump, Numer.
+ * Algorithms 59, 2012): each column of L and of R is scaled by a power of two
+ * below its largest magnitude and cut into `slices` digits of 7 bits
+ * (rounded to nearest, in [-127, 127]); the digit products with t + u <=
+ * slices + 1 are exact in int32 and their levels are added in float64 from
+ * the smallest. Error per element below n (slices + 2) 2^(e_i + f_j - 7 slices)
+ * plus float64 rounding (2^e_i, 2^f_j: the column scales); 9 slices match a
+ * float64 product for the iteration. Costs slices (slices + 1) / 2 int8
+ * products. Ownership and stream as ipr_gemm; dD must not alias an operand.
+ * dWork >= ipr_gemm_emul_workspace(n, slices) bytes (device). Errors:
+ * IPR_EARG for a null pointer, n < 1, slices outside 1..12, n above 132864
+ * (one digit product must fit an int32 accumulation) or a short workspace.
+ * A column holding Inf or NaN gives NaN in the matching row or column of D. */
+int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int slices,
+                  void* dWork, size_t work_bytes, hipStream_t stream);
+size_t ipr_gemm_emul_workspace(int n, int slices);
+
 /* ||A||_1 and ||A||_inf (eq. (3)) into host out[0], out[1]. dWork >= n*(n/256+2)*8 bytes. */
 int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
               hipStream_t stream);

@@ -77,6 +77,9 @@ _SIGS = {
     "ipr_gemm_lowp": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
                                  ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ipr_gemm_lowp_workspace": (ct.c_size_t, [ct.c_int]),
+    "ipr_gemm_emul": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
+                                 ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "ipr_gemm_emul_workspace": (ct.c_size_t, [ct.c_int, ct.c_int]),
     "ipr_norms": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                              ct.c_void_p]),
     "ipr_features": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
@@ -276,6 +279,23 @@ def ipr_gemm_lowp(L, R, dtype, out=None, workspace=None, stream=None):
     D = out if out is not None else torch.empty_like(L)
     ws = workspace if workspace is not None else _workspace(ipr_gemm_lowp_workspace(n), L.device)
     _check(_fn("ipr_gemm_lowp")(_ptr(L), _ptr(R), _ptr(D), n, int(dtype), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return D
+
+
+def ipr_gemm_emul_workspace(n, slices=9) -> int:
+    return int(_fn("ipr_gemm_emul_workspace")(n, slices))
+
+
+def ipr_gemm_emul(L, R, slices=9, out=None, workspace=None, stream=None):
+    """D = L^T R, FP64-accurate, from int8 digit slices on the matrix cores."""
+    n = L.shape[0]
+    for t, nm in ((L, "L"), (R, "R")):
+        _need(t, torch.float64, (n, n), nm)
+    D = out if out is not None else torch.empty_like(L)
+    ws = workspace if workspace is not None else _workspace(
+        ipr_gemm_emul_workspace(n, slices), L.device)
+    _check(_fn("ipr_gemm_emul")(_ptr(L), _ptr(R), _ptr(D), n, int(slices), _ptr(ws), ws.numel(),
                                 _stream(stream)))
     return D
 

@@ -24,6 +24,8 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int TILE = 128;
 constexpr int kZeroTile = -(1 << 20);   // exponent of an all-zero tile
@@ -167,6 +169,47 @@ __global__ __launch_bounds__(NT) void quantize_t_kernel(const double* __restrict
   }
 }
 
+// One launch of the int8-slice product covers one chunk of the pairs (t, u)
+// of one level g = t + u (see gemm_slices): digit slices t of L^T and u of
+// R^T, concatenated along k, accumulate exactly in int32.
+struct SliceArgs {
+  int npairs;               // pairs in this chunk
+  unsigned long long tpk;   // slice index of L^T for pair q in bits 4q .. 4q + 3
+  unsigned long long upk;   // same for R^T
+  size_t slice_bytes;       // bytes of one digit matrix
+  double* P;                // exact partial sum of a level split into chunks
+  double* S;                // running float64 sum of the finished levels
+  int first_chunk, last_chunk, first_level, final_level;
+  int shift;                // beta g
+};
+
+constexpr int kNonFinite = 0x7fffffff;  // row exponent of a row holding Inf or NaN
+
+// Element (i, j) of a chunk's int32 result: exact level sum, then the scaled
+// level added to the running sum (smallest level first); the last level goes
+// through the product epilogue.
+__device__ __forceinline__ void slice_element(const SliceArgs& sa, const int* EL, const int* ER,
+                                              const Epilogue& e, int n, int tri, int i, int j,
+                                              int iv, double& psum) {
+  if (i >= n || j >= n) return;
+  const size_t ij = (size_t)i * n + j;
+  double v = (double)iv;
+  if (!sa.first_chunk) v += sa.P[ij];   // integers below 2^53: exact
+  if (!sa.last_chunk) {
+    sa.P[ij] = v;
+    return;
+  }
+  const int ei = EL[i], ej = ER[j];
+  double term = (ei == kNonFinite || ej == kNonFinite) ? __builtin_nan("")
+                                                       : ldexp(v, ei + ej - sa.shift);
+  if (!sa.first_level) term = sa.S[ij] + term;
+  if (!sa.final_level) {
+    sa.S[ij] = term;
+    return;
+  }
+  epilogue_element(e, n, tri, i, j, term, psum);
+}
+
 // D = L^T R from k-contiguous codes Lt (row i), Rt (row j), order np (a
 // multiple of 256), on 256 x 256 output tiles.
 //
@@ -208,7 +251,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
                                                         const uint8_t* __restrict__ Rt,
                                                         const int* __restrict__ EL,
                                                         const int* __restrict__ ER, int n,
-                                                        int np, Grid gr, int tri, Epilogue e) {
+                                                        int np, Grid gr, int tri, Epilogue e,
+                                                        SliceArgs sa) {
   // one array per ring slot: distinct objects let the compiler see that the
   // loads in flight into other slots do not alias the slot being read
   __shared__ __attribute__((aligned(16))) uint8_t A0[STG_BYTES], A1[STG_BYTES], A2[STG_BYTES],
@@ -259,6 +303,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
   // the blocked layout holds each stage's 256 x 64 bytes contiguously and in
   // LDS order: lane l of instruction q copies bytes (64 w + 16 q) 64 + 16 l
   const int nst_all = (int)(ldb / KB);
+  const int nst1 = nst_all;   // stages per operand pair
   const uint8_t* gA[4];
   const uint8_t* gB[4];
 #pragma unroll
@@ -271,14 +316,22 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
     constexpr int sl = decltype(S)::value;
     uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
     uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
-    const size_t kb0 = (size_t)st * (BT * KB);   // stage st's block
+    size_t ka0, kb0;   // stage st's block of each operand
+    if constexpr (DT == LP_I8) {
+      const int pr = st / nst1;   // pair
+      const size_t off = (size_t)(st - pr * nst1) * (BT * KB);
+      ka0 = off + (size_t)((sa.tpk >> (4 * pr)) & 15) * sa.slice_bytes;
+      kb0 = off + (size_t)((sa.upk >> (4 * pr)) & 15) * sa.slice_bytes;
+    } else {
+      ka0 = kb0 = (size_t)st * (BT * KB);
+    }
     // LDS destinations as plain addresses (wave-uniform, in scalar registers)
     const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)as);
     const uint32_t lb = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)bs);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t off = (64 * wave + 16 * q) * KB;
-      __builtin_amdgcn_global_load_lds((const void*)(gA[q] + kb0), (lds_void*)(uintptr_t)(la + off),
+      __builtin_amdgcn_global_load_lds((const void*)(gA[q] + ka0), (lds_void*)(uintptr_t)(la + off),
                                        16, 0, 0);
       __builtin_amdgcn_global_load_lds((const void*)(gB[q] + kb0), (lds_void*)(uintptr_t)(lb + off),
                                        16, 0, 0);
@@ -299,7 +352,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
     const uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
     const uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
     const int kt = st / ST_PER_KT;
-    if constexpr (ESZ == 2) {
+    if constexpr (ESZ == 2 || DT == LP_I8) {
       _Float16 fsc = (_Float16)1.0f;
       bool scale_a = false;
       if constexpr (DT == LP_FP16) {
@@ -349,12 +402,18 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
               acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                   __builtin_bit_cast(v8bf, av[cur][a]), __builtin_bit_cast(v8bf, bv[cur][b]),
                   acc[a][b], 0, 0, 0);
+            else if constexpr (DT == LP_I8)
+              // int32 results kept in the float accumulators' registers as bits
+              acc[a][b] = __builtin_bit_cast(
+                  v16f, __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            __builtin_bit_cast(v4i, av[cur][a]), __builtin_bit_cast(v4i, bv[cur][b]),
+                            __builtin_bit_cast(v16i, acc[a][b]), 0, 0, 0));
             else
               acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                   __builtin_bit_cast(v8h, av[cur][a]), __builtin_bit_cast(v8h, bv[cur][b]),
                   acc[a][b], 0, 0, 0);
           }
-        if constexpr (DT == LP_BF16) {
+        if constexpr (DT == LP_BF16 || DT == LP_I8) {
           if (ks + 1 < KB / 32) {
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
@@ -413,7 +472,8 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
     compute(S, st);
   };
 
-  const int nst = (int)(ldb / KB);  // a multiple of 4 (np is a multiple of 256)
+  // a multiple of 4 (np is a multiple of 256)
+  const int nst = (int)(ldb / KB) * (DT == LP_I8 ? sa.npairs : 1);
   issue(Ic<0>{}, 0);
   issue(Ic<1>{}, 1);
   issue(Ic<2>{}, 2);
@@ -447,17 +507,100 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
       for (int r = 0; r < 16; ++r) {
         const int row = wm * 32 + (r & 3) + 8 * (r >> 2) + 4 * fhalf;
         const int col = wn * 128 + b * 32 + frow;
+        // (int8 products: the int32 bits travel as a float, moved, never computed on)
         *stg_at(row, col) = acc[h][b][r];
       }
     wg_barrier();
     for (int q = 0; q < 64; ++q) {
       const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
       const int j = j0 + tid;
-      const double post = post_sh[(q >> 5) * 2 + (tid >> 7)];  // the owning wave's
-      epilogue_element(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
+      if constexpr (DT == LP_I8) {
+        slice_element(sa, EL, ER, e, n, tri, i, j, __float_as_int(*stg_at(q, tid)), psum);
+      } else {
+        const double post = post_sh[(q >> 5) * 2 + (tid >> 7)];  // the owning wave's
+        epilogue_element(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
+      }
     }
   }
   if (e.partial) store_partial(e.partial, lw, psum, red);
+  }
+}
+
+// ---- FP64-accurate products from int8 digit slices ----------------------
+//
+// Error-free splitting (Ozaki, Ogita, Oishi and Rump, Numer. Algorithms 59,
+// 2012) with beta = 7-bit digits: row i of an operand is scaled by 2^-e_i,
+// e_i the smallest integer above its largest magnitude's exponent, and cut
+// into s digits d_t = round(2^7 r) (nearest, ties to even, clamped to
+// [-127, 127]), r the remainder of the previous digit. The digit matrices
+// multiply exactly on the int8 matrix cores; level g = t + u sums the pairs
+// of slices (t, u), g <= s + 1, exactly in int32; the levels are scaled and
+// added in float64 from the smallest to the largest.
+
+// Largest magnitude of each column of X as the bit pattern of a double
+// (non-negative doubles order like their bits); Inf and NaN count as Inf.
+__global__ __launch_bounds__(NT) void colmax_kernel(const double* __restrict__ X, int n,
+                                                    int rows, unsigned long long* __restrict__ cm) {
+  const int c = blockIdx.x * NT + threadIdx.x;
+  if (c >= n) return;
+  const int r0 = blockIdx.y * rows, r1 = min(n, r0 + rows);
+  double m = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    const double a = fabs(X[(size_t)r * n + c]);
+    m = a <= 1.79769313486231570815e308 ? fmax(m, a) : __builtin_inf();
+  }
+  atomicMax(&cm[c], (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ __launch_bounds__(NT) void zero_u64_kernel(unsigned long long* __restrict__ v, int n) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i < n) v[i] = 0ull;
+}
+
+// One workgroup per 64 x 64 tile (k rows, i columns) of X: digits of column
+// i of X (= row i of the transposed operand), 16 consecutive k per thread,
+// written as one 16-byte piece per slice in the blocked code layout. Covers
+// the padded order np (zeros beyond n). Blocks of the first k tile also
+// write the row exponents.
+constexpr int SB = 64;
+__global__ __launch_bounds__(NT) void split_kernel(const double* __restrict__ X, int n, int np,
+                                                   int s, const unsigned long long* __restrict__ cm,
+                                                   uint8_t* __restrict__ Q, size_t slice_bytes,
+                                                   int* __restrict__ E) {
+  __shared__ double xs[SB][SB + 1];
+  const int k0 = blockIdx.y * SB, i0 = blockIdx.x * SB;
+  for (int t = threadIdx.x; t < SB * SB; t += NT) {
+    const int r = t / SB, c = t % SB;
+    const int k = k0 + r, i = i0 + c;
+    xs[r][c] = (k < n && i < n) ? X[(size_t)k * n + i] : 0.0;
+  }
+  __syncthreads();
+  const int il = threadIdx.x >> 2, piece = threadIdx.x & 3;
+  const int i = i0 + il;
+  int e = 0;
+  bool bad = false;
+  if (i < n) {
+    const double m = __longlong_as_double((long long)cm[i]);
+    if (!(m <= 1.79769313486231570815e308))
+      bad = true;
+    else if (m > 0.0)
+      e = ilogb(m) + 1;   // smallest e with m < 2^e
+  }
+  if (blockIdx.y == 0 && piece == 0) E[i] = bad ? kNonFinite : e;
+  double r[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) r[kk] = bad ? 0.0 : ldexp(xs[piece * 16 + kk][il], -e);
+  const size_t at = lp_block_offset(i, k0 + piece * 16, np / KB);
+  for (int t = 0; t < s; ++t) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double v = r[kk] * 128.0;   // exact
+      const double d = fmin(127.0, fmax(-127.0, rint(v)));
+      r[kk] = v - d;                    // exact
+      w[kk >> 2] |= ((uint32_t)(int)d & 0xffu) << (8 * (kk & 3));
+    }
+    *reinterpret_cast<uint4*>(Q + (size_t)t * slice_bytes + at) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
@@ -506,17 +649,89 @@ hipError_t gemm_lp(const void* Lq, const int* EL, const void* Rq, const int* ER,
   switch (dtype) {
     case LP_BF16:
       hipLaunchKernelGGL((gemm_lp_kernel<2, LP_BF16>), dim3(grid), dim3(NT), 0, stream, L, R,
-                         EL, ER, n, np, gr, tri, e);
+                         EL, ER, n, np, gr, tri, e, SliceArgs{});
       break;
     case LP_FP16:
       hipLaunchKernelGGL((gemm_lp_kernel<2, LP_FP16>), dim3(grid), dim3(NT), 0, stream, L, R,
-                         EL, ER, n, np, gr, tri, e);
+                         EL, ER, n, np, gr, tri, e, SliceArgs{});
       break;
     default:
       hipLaunchKernelGGL((gemm_lp_kernel<1, LP_FP8>), dim3(grid), dim3(NT), 0, stream, L, R,
-                         EL, ER, n, np, gr, tri, e);
+                         EL, ER, n, np, gr, tri, e, SliceArgs{});
   }
   return hipGetLastError();
+}
+
+size_t slice_bytes(int n) {
+  const size_t np = lp_padded(n);
+  return np * np;
+}
+
+int slice_max_n() {
+  // one pair of digit matrices must fit an int32 accumulation: np 127^2 < 2^31
+  return (int)(2147483647ll / (127ll * 127ll) / BT * BT);
+}
+
+hipError_t slices_split(const double* X, int n, int s, void* Q, int* E, unsigned long long* cm,
+                        hipStream_t stream) {
+  if (!X || !Q || !E || !cm || s < 1 || s > kMaxSlices) return hipErrorInvalidValue;
+  const int np = lp_padded(n);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + NT - 1) / NT), dim3(NT), 0, stream, cm, n);
+  const int rows = 256;
+  hipLaunchKernelGGL(colmax_kernel, dim3((n + NT - 1) / NT, (n + rows - 1) / rows), dim3(NT), 0,
+                     stream, X, n, rows, cm);
+  hipLaunchKernelGGL(split_kernel, dim3(np / SB, np / SB), dim3(NT), 0, stream, X, n, np, s, cm,
+                     (uint8_t*)Q, slice_bytes(n), E);
+  return hipGetLastError();
+}
+
+hipError_t gemm_slices(const void* Lq, const int* EL, const void* Rq, const int* ER, int n, int s,
+                       double* P, double* S, int tri, const Epilogue& e, hipStream_t stream) {
+  if (!Lq || !Rq || !EL || !ER || !P || !S || s < 1 || s > kMaxSlices) return hipErrorInvalidValue;
+  const int np = lp_padded(n);
+  // pairs per int32 accumulation (cap np 127^2 < 2^31); a level with more
+  // pairs is split into chunks whose sums meet exactly in P
+  const long long cap = 2147483647ll / (127ll * 127ll * np);
+  if (cap < 1) return hipErrorInvalidValue;
+  Grid gr = make_grid(n, tri, BT);
+  static thread_local int ncu = 0;
+  if (!ncu) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+  }
+  const int grid = std::max(8, std::min(gr.nwg, ncu / 8 * 8));
+  const Epilogue none;
+  for (int g = s + 1; g >= 2; --g) {
+    const int t_lo = std::max(1, g - s), t_hi = std::min(s, g - 1);
+    const int pairs = t_hi - t_lo + 1;
+    const int per = (int)std::min<long long>(cap, 15);
+    for (int c0 = 0; c0 < pairs; c0 += per) {
+      SliceArgs sa{};
+      sa.npairs = std::min(per, pairs - c0);
+      for (int q = 0; q < sa.npairs; ++q) {
+        const int t = t_lo + c0 + q, u = g - t;   // 1-based digit indices
+        sa.tpk |= (unsigned long long)(t - 1) << (4 * q);
+        sa.upk |= (unsigned long long)(u - 1) << (4 * q);
+      }
+      sa.slice_bytes = slice_bytes(n);
+      sa.P = P;
+      sa.S = S;
+      sa.first_chunk = c0 == 0;
+      sa.last_chunk = c0 + sa.npairs >= pairs;
+      sa.first_level = g == s + 1;
+      sa.final_level = g == 2;
+      sa.shift = 7 * g;
+      const bool fin = sa.final_level && sa.last_chunk;
+      hipLaunchKernelGGL((gemm_lp_kernel<1, LP_I8>), dim3(grid), dim3(NT), 0, stream,
+                         (const uint8_t*)Lq, (const uint8_t*)Rq, EL, ER, n, np, gr, tri,
+                         fin ? e : none, sa);
+      const hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace ipr
