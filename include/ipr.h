@@ -80,7 +80,11 @@ typedef enum {
   IPR_FP64 = 0,
   IPR_BF16 = 1,      /* bf16 operands, fp32 accumulation */
   IPR_FP16 = 2,      /* fp16 operands with per-128x128-tile power-of-two scales, fp32 accumulation */
-  IPR_FP8_E4M3 = 3   /* fp8 e4m3 operands with per-128x128-tile power-of-two scales, fp32 accumulation */
+  IPR_FP8_E4M3 = 3,  /* fp8 e4m3 operands with per-128x128-tile power-of-two scales, fp32 accumulation */
+  IPR_FP64_INT8_EMUL = 4 /* every product of the iteration FP64-accurate from int8 digit slices
+                            (ipr_gemm_emul, schedule.emul_slices digits): no refinement phase;
+                            the start's squarings and the final check stay on the FP64 cores;
+                            n <= 132864 */
 } ipr_dtype;
 
 typedef struct {
@@ -104,6 +108,8 @@ typedef struct {
                           the plain iteration of eq. (1)); see ipr_solve */
   int evaluation;      /* ipr_evaluation (default COUPLED); LITERAL and NEWTON_SCHULZ need the FP64
                           bulk dtype and ipr_solve (not the batched solver) */
+  int emul_slices;     /* IPR_FP64_INT8_EMUL: 7-bit digits per operand, 1..12 (0: 9, which matches
+                          FP64 products for the iteration) */
 } ipr_schedule;
 
 typedef struct {
@@ -124,8 +130,10 @@ typedef struct {
   int gemm_launches;   /* products timed (schedule.timing = 1) */
   double ms_gemm;      /* their summed device time */
   double gemm_flops;   /* their algorithmic flops: 2 n^3 per full product, n^2 (n + 1) per triangle */
-  int lp_gemm_launches;  /* the same for the low-precision products of the bulk phase */
-  double ms_lp_gemm;     /* (matrix-core kernel only; the rounding of operands is not included) */
+  int lp_gemm_launches;  /* the same for the low-precision products of the bulk phase and the
+                            int8-slice products of IPR_FP64_INT8_EMUL (one per product) */
+  double ms_lp_gemm;     /* (matrix-core kernels only; the rounding or splitting of operands is
+                            not included) */
   double lp_gemm_flops;
   double lmin_est;       /* dynamic_scaling: the Lanczos estimate of lambda_min(A) (0 otherwise) */
   int reest_iter;        /* dynamic_scaling: the step before which lambda_min(M_k) was estimated

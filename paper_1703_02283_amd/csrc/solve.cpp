@@ -118,11 +118,21 @@ struct Work {
   double* scal;
   void* lq[NLP];
   int* le[NLP];
+  // int8-slice products: digit matrices of L^T and R^T in lq[0], lq[1]
+  unsigned long long* cm;
+  double* slP;
+  double* slS;
 };
+
+// digits per operand of the int8-slice products (0 when the dtype does not use them)
+int emul_digits(const ipr_schedule& s) {
+  if (s.bulk_dtype != IPR_FP64_INT8_EMUL) return 0;
+  return s.emul_slices ? s.emul_slices : 9;
+}
 
 int n_mats(int p) { return p == 1 ? 5 : (p == 2 ? 6 : NMAT); }
 
-size_t carve(int n, int p, int dtype, Work* w, void* base, size_t cap, bool* ok) {
+size_t carve(int n, int p, int dtype, int slices, Work* w, void* base, size_t cap, bool* ok) {
   Carver c(base, cap);
   const size_t nn = (size_t)n * n;
   const int nm = n_mats(p);
@@ -133,11 +143,18 @@ size_t carve(int n, int p, int dtype, Work* w, void* base, size_t cap, bool* ok)
   const size_t strips = (n + 255) / 256;
   w->norms_scratch = c.take<double>(2 * (size_t)n + strips * n);
   w->scal = c.take<double>(64);
+  const bool emul = dtype == IPR_FP64_INT8_EMUL;
   for (int i = 0; i < NLP; ++i) {
-    const bool lp = dtype != IPR_FP64;
-    w->lq[i] = lp ? (void*)c.take<uint8_t>(lp_bytes(n, dtype)) : nullptr;
-    w->le[i] = lp ? c.take<int>(lp_exp_count(n)) : nullptr;
+    const bool lp = dtype != IPR_FP64 && !emul;
+    const bool sl = emul && i < 2;
+    w->lq[i] = lp   ? (void*)c.take<uint8_t>(lp_bytes(n, dtype))
+               : sl ? (void*)c.take<uint8_t>((size_t)slices * slice_bytes(n))
+                    : nullptr;
+    w->le[i] = lp ? c.take<int>(lp_exp_count(n)) : sl ? c.take<int>(lp_padded(n)) : nullptr;
   }
+  w->cm = emul ? c.take<unsigned long long>(n) : nullptr;
+  w->slP = emul ? c.take<double>(nn) : nullptr;
+  w->slS = emul ? c.take<double>(nn) : nullptr;
   *ok = c.ok();
   return c.used;
 }
@@ -166,6 +183,7 @@ struct Prod {
   int n;
   hipStream_t st;
   int lowp_dtype = 0;  // 0: FP64 products
+  int emul = 0;        // > 0: int8-slice products with this many digits
   Work* w;
   int gemms = 0;
   bool timing = false;
@@ -204,10 +222,12 @@ struct Prod {
   }
   // a product in FP64 whatever the phase
   hipError_t f64(const double* L, const double* R, int tri, const Epilogue& e) {
-    const int keep = lowp_dtype;
+    const int keep = lowp_dtype, keep_e = emul;
     lowp_dtype = 0;
+    emul = 0;
     hipError_t err = (*this)(L, R, tri, e);
     lowp_dtype = keep;
+    emul = keep_e;
     return err;
   }
   hipError_t operator()(const double* L, const double* R, int tri, const Epilogue& e) {
@@ -221,10 +241,20 @@ struct Prod {
       ev.push_back(e0);
       ev.push_back(e1);
       flops.push_back(tri ? (double)n * n * (n + 1.0) : 2.0 * n * n * (double)n);
-      is_lp.push_back(lowp_dtype != 0);
+      is_lp.push_back(lowp_dtype != 0 || emul != 0);
       return hipEventRecord(e0, st);
     };
-    if (!lowp_dtype) {
+    if (emul) {
+      // split afresh for every product (about 1% of its time): no cached
+      // digits can go stale behind a kernel that rewrites an operand
+      if ((err = slices_split(L, n, emul, w->lq[0], w->le[0], w->cm, st)) != hipSuccess) return err;
+      const int b = R == L ? 0 : 1;
+      if (b && (err = slices_split(R, n, emul, w->lq[1], w->le[1], w->cm, st)) != hipSuccess)
+        return err;
+      if ((err = start()) != hipSuccess) return err;
+      err = gemm_slices(w->lq[0], w->le[0], w->lq[b], w->le[b], n, emul, w->slP, w->slS, tri, e,
+                        st);
+    } else if (!lowp_dtype) {
       if ((err = start()) != hipSuccess) return err;
       err = gemm_f64(L, R, n, tri, e, st);
     } else {
@@ -242,7 +272,7 @@ struct Prod {
   }
   // partial sums written by the last product (the kernels' grids differ)
   int slots(int tri) const {
-    return lowp_dtype ? lp_partial_slots(n, tri) : gemm_partial_slots(n, tri);
+    return (lowp_dtype || emul) ? lp_partial_slots(n, tri) : gemm_partial_slots(n, tri);
   }
   // after the stream has drained
   void totals(int lp, int* count, double* ms, double* fl) const {
@@ -520,7 +550,8 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
   Work w;
   bool ok;
   const int dt = s ? s->bulk_dtype : IPR_FP64;
-  const size_t single = carve(n_max, p_max, dt, &w, nullptr, (size_t)-1, &ok) + 256;
+  const int sl = s ? emul_digits(*s) : 0;
+  const size_t single = carve(n_max, p_max, dt, sl, &w, nullptr, (size_t)-1, &ok) + 256;
   return std::max(single, batched_workspace_bytes(n_max, batch));
 }
 
@@ -575,14 +606,21 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     return fail(IPR_EARG, "ipr_solve: the Newton-Schulz order is the p = 1 case");
   if (s.evaluation != IPR_EVAL_COUPLED && s.bulk_dtype != IPR_FP64)
     return fail(IPR_EARG, "ipr_solve: the literal and Newton-Schulz orders run in FP64 only");
-  if (s.bulk_dtype < IPR_FP64 || s.bulk_dtype > IPR_FP8_E4M3)
+  if (s.bulk_dtype < IPR_FP64 || s.bulk_dtype > IPR_FP64_INT8_EMUL)
     return fail(IPR_EARG, "ipr_solve: unknown bulk dtype %d", s.bulk_dtype);
+  const int slices = emul_digits(s);
+  if (s.bulk_dtype == IPR_FP64_INT8_EMUL) {
+    if (slices < 1 || slices > kMaxSlices)
+      return fail(IPR_EARG, "ipr_solve: emul_slices must be in 1..%d", kMaxSlices);
+    if (n > slice_max_n())
+      return fail(IPR_EARG, "ipr_solve: int8-slice products need n <= %d", slice_max_n());
+  }
   if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
     return fail(IPR_EARG, "ipr_solve: the learned start needs schedule.mlp_params");
 
   Solver sv;
   bool ok;
-  carve(n, p, s.bulk_dtype, &sv.w, dWork, work_bytes, &ok);
+  carve(n, p, s.bulk_dtype, slices, &sv.w, dWork, work_bytes, &ok);
   if (!ok)
     return fail(IPR_EARG, "ipr_solve: workspace too small (%zu bytes, need %zu)", work_bytes,
                 ipr_workspace_size(n, p, 1, sched));
@@ -595,6 +633,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   sv.prod.st = stream;
   sv.prod.w = &sv.w;
   sv.prod.timing = s.timing != 0;
+  sv.prod.emul = slices;
   Work& w = sv.w;
   sv.Cb[0] = dC;
   sv.Cb[1] = w.m[0];
@@ -730,7 +769,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   // by the start, and mu_k mod_b < 2 keeps every step inside eq. (2). Once the
   // residual is below 1 it bounds both ends, and from a lower end of 1/2 on
   // the steps are unscaled. mu_0 is folded into the start's scale.
-  bool dyn = s.dynamic_scaling && init == IPR_INIT_IDENTITY && s.bulk_dtype == IPR_FP64 &&
+  bool dyn = s.dynamic_scaling && init == IPR_INIT_IDENTITY &&
+             (s.bulk_dtype == IPR_FP64 || s.bulk_dtype == IPR_FP64_INT8_EMUL) &&
              s.evaluation == IPR_EVAL_COUPLED && n >= 32;
   double mod_a = 0.0, mod_b = 1.0, mu_k = 1.0;
   if (dyn) {
@@ -779,7 +819,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   tm.mark(2);
 
   // ---- iterations: optional low-precision bulk phase, then FP64
-  const bool lowp = s.bulk_dtype != IPR_FP64;
+  // (int8-slice products are FP64-accurate: no low-precision phase)
+  const bool lowp = s.bulk_dtype != IPR_FP64 && s.bulk_dtype != IPR_FP64_INT8_EMUL;
   bool lp_restart = false;
   int status = IPR_EMAXITER;
   int k = 0, kb = 0;

@@ -118,3 +118,61 @@ def test_emul_argument_errors(ipr):
     with pytest.raises(ipr.IprError):
         ipr.ipr_gemm_emul(a, b, 9, workspace=small)
     assert ipr.ipr_gemm_emul_workspace(64, 0) == 0
+
+
+# ---- the iteration with every product from int8 slices ---------------------
+
+def emul_schedule(ipr, **kw):
+    return ipr.ipr_schedule_default(bulk_dtype=ipr.IPR_FP64_INT8_EMUL, timing=1, **kw)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("n", [300, 517])
+def test_emul_solve_reaches_the_root(ipr, n, p):
+    from oracle import iteration as it
+    say("emul solve", n, p)
+    a, _, _ = w.spd_log_spectrum(n, 1e4, seed=70 + p)
+    ref = it.eig_root(a, p)
+    C, res = ipr.ipr_solve(dev(a), p, 1e-10, schedule=emul_schedule(ipr))
+    _, r64 = ipr.ipr_solve(dev(a), p, 1e-10)
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert res.residual_true < 1e-10
+    assert it.rel_fro(host(C), ref) <= 1e-10
+    assert res.iters_bulk == 0 and abs(res.iters_fp64 - r64.iters_fp64) <= 1
+    # the iteration's products ran on the int8 matrix cores; the FP64 cores
+    # did only the final check (p products)
+    assert res.lp_gemm_launches >= res.iters_fp64
+    assert res.gemm_launches <= p
+
+
+def test_emul_headline_schedule_n1024(ipr):
+    from oracle import iteration as it
+    say("emul headline n=1024")
+    a, _ = w.householder_spd(1024, 1e4, seed=0)
+    s = emul_schedule(ipr, scale_squarings=6, dynamic_scaling=1)
+    C, res = ipr.ipr_solve(dev(a), 2, 1e-10, schedule=s)
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert res.residual_true < 1e-10
+    assert it.rel_fro(host(C), it.eig_root(a, 2)) <= 1e-10
+
+
+def test_emul_few_slices_floor_and_report_it(ipr):
+    """Four digits (28 bits) cannot carry the iteration to 1e-10: the solve
+    stops above it (on its floor) rather than claiming convergence."""
+    say("emul 4 slices")
+    a, _, _ = w.spd_log_spectrum(300, 1e2, seed=3)
+    C, res = ipr.ipr_solve(dev(a), 2, 1e-10, schedule=emul_schedule(ipr, emul_slices=4),
+                           raise_on=(ipr.IPR_EARG, ipr.IPR_EHIP))
+    assert res.status != ipr.IPR_OK, res.as_dict()
+
+
+def test_emul_argument_errors_of_the_solve(ipr):
+    say("emul solve errors")
+    a = dev(np.eye(64) * 2.0)
+    for kw in ({"emul_slices": 13}, {"emul_slices": -1},
+               {"evaluation": ipr.IPR_EVAL_LITERAL}):
+        with pytest.raises(ipr.IprError):
+            ipr.ipr_solve(a, 2, 1e-10, schedule=emul_schedule(ipr, **kw))
+    A = torch.eye(64, dtype=torch.float64, device="cuda").reshape(-1) * 2.0
+    with pytest.raises(ipr.IprError):
+        ipr.ipr_solve_batched(A, [0], [64], [2], 1e-10, schedule=emul_schedule(ipr))
