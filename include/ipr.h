@@ -108,8 +108,8 @@ typedef struct {
                           the plain iteration of eq. (1)); see ipr_solve */
   int evaluation;      /* ipr_evaluation (default COUPLED); LITERAL and NEWTON_SCHULZ need the FP64
                           bulk dtype and ipr_solve (not the batched solver) */
-  int emul_slices;     /* IPR_FP64_INT8_EMUL: 7-bit digits per operand, 1..12 (0: 9, which matches
-                          FP64 products for the iteration) */
+  int emul_slices;     /* IPR_FP64_INT8_EMUL: 7-bit digits per operand, 1..12 (0: 10, which
+                          reaches the FP64 result at n = 16384; see ipr_gemm_emul) */
 } ipr_schedule;
 
 typedef struct {
@@ -222,9 +222,11 @@ size_t ipr_gemm_lowp_workspace(int n);
  * (rounded to nearest, in [-127, 127]); the digit products with t + u <=
  * slices + 1 are exact in int32 and their levels are added in float64 from
  * the smallest. Error per element below n (slices + 2) 2^(e_i + f_j - 7 slices)
- * plus float64 rounding (2^e_i, 2^f_j: the column scales); 9 slices match a
- * float64 product for the iteration. Costs slices (slices + 1) / 2 int8
- * products. Ownership and stream as ipr_gemm; dD must not alias an operand.
+ * plus float64 rounding (2^e_i, 2^f_j: the column scales). An entry far below
+ * its column's largest keeps fewer bits than float64 gives it: with 9 slices
+ * the n = 8192 and 16384 iterations (kappa = 1e4) stop near 1e-10 instead of
+ * 3e-11; 10 slices reach the float64 result. Costs slices (slices + 1) / 2
+ * int8 products. Ownership and stream as ipr_gemm; dD must not alias an operand.
  * dWork >= ipr_gemm_emul_workspace(n, slices) bytes (device). Errors:
  * IPR_EARG for a null pointer, n < 1, slices outside 1..12, n above 132864
  * (one digit product must fit an int32 accumulation) or a short workspace.

@@ -284,11 +284,11 @@ def ipr_gemm_lowp(L, R, dtype, out=None, workspace=None, stream=None):
     return D
 
 
-def ipr_gemm_emul_workspace(n, slices=9) -> int:
+def ipr_gemm_emul_workspace(n, slices=10) -> int:
     return int(_fn("ipr_gemm_emul_workspace")(n, slices))
 
 
-def ipr_gemm_emul(L, R, slices=9, out=None, workspace=None, stream=None):
+def ipr_gemm_emul(L, R, slices=10, out=None, workspace=None, stream=None):
     """D = L^T R, FP64-accurate, from int8 digit slices on the matrix cores."""
     n = L.shape[0]
     for t, nm in ((L, "L"), (R, "R")):

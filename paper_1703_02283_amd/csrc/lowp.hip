@@ -185,16 +185,17 @@ struct SliceArgs {
 
 constexpr int kNonFinite = 0x7fffffff;  // row exponent of a row holding Inf or NaN
 
-// Element (i, j) of a chunk's int32 result: exact level sum, then the scaled
-// level added to the running sum (smallest level first); the last level goes
-// through the product epilogue.
+// Element (i, j) of a chunk's int32 result iv, with the values already read
+// from P (pv: the level's exact partial sum) and S (sv: the running sum):
+// exact level sum, then the scaled level added to the running sum (smallest
+// level first); the last level goes through the product epilogue.
 __device__ __forceinline__ void slice_element(const SliceArgs& sa, const int* EL, const int* ER,
                                               const Epilogue& e, int n, int tri, int i, int j,
-                                              int iv, double& psum) {
+                                              int iv, double pv, double sv, double& psum) {
   if (i >= n || j >= n) return;
   const size_t ij = (size_t)i * n + j;
   double v = (double)iv;
-  if (!sa.first_chunk) v += sa.P[ij];   // integers below 2^53: exact
+  if (!sa.first_chunk) v += pv;   // integers below 2^53: exact
   if (!sa.last_chunk) {
     sa.P[ij] = v;
     return;
@@ -202,7 +203,7 @@ __device__ __forceinline__ void slice_element(const SliceArgs& sa, const int* EL
   const int ei = EL[i], ej = ER[j];
   double term = (ei == kNonFinite || ej == kNonFinite) ? __builtin_nan("")
                                                        : ldexp(v, ei + ej - sa.shift);
-  if (!sa.first_level) term = sa.S[ij] + term;
+  if (!sa.first_level) term = sv + term;
   if (!sa.final_level) {
     sa.S[ij] = term;
     return;
@@ -511,12 +512,35 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
         *stg_at(row, col) = acc[h][b][r];
       }
     wg_barrier();
-    for (int q = 0; q < 64; ++q) {
-      const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
+    if constexpr (DT == LP_I8) {
+      // the partial and running sums of 16 rows are read before any is
+      // written: the stores may alias the loads as far as the compiler
+      // knows, and one round trip to memory per element would serialise
+      const bool need_p = !sa.first_chunk, need_s = sa.last_chunk && !sa.first_level;
       const int j = j0 + tid;
-      if constexpr (DT == LP_I8) {
-        slice_element(sa, EL, ER, e, n, tri, i, j, __float_as_int(*stg_at(q, tid)), psum);
-      } else {
+      for (int q0 = 0; q0 < 64; q0 += 16) {
+        double pv[16], sv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int q = q0 + u;
+          const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
+          const bool in = i < n && j < n;
+          const size_t ij = (size_t)i * n + j;
+          pv[u] = in && need_p ? sa.P[ij] : 0.0;
+          sv[u] = in && need_s ? sa.S[ij] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int q = q0 + u;
+          const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
+          slice_element(sa, EL, ER, e, n, tri, i, j, __float_as_int(*stg_at(q, tid)), pv[u],
+                        sv[u], psum);
+        }
+      }
+    } else {
+      for (int q = 0; q < 64; ++q) {
+        const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
+        const int j = j0 + tid;
         const double post = post_sh[(q >> 5) * 2 + (tid >> 7)];  // the owning wave's
         epilogue_element(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
       }

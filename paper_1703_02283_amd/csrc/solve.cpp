@@ -127,7 +127,7 @@ struct Work {
 // digits per operand of the int8-slice products (0 when the dtype does not use them)
 int emul_digits(const ipr_schedule& s) {
   if (s.bulk_dtype != IPR_FP64_INT8_EMUL) return 0;
-  return s.emul_slices ? s.emul_slices : 9;
+  return s.emul_slices ? s.emul_slices : 10;
 }
 
 int n_mats(int p) { return p == 1 ? 5 : (p == 2 ? 6 : NMAT); }

@@ -78,3 +78,27 @@ def test_kernel_matrix_4096(ipr, kernel4096, p):
     assert res.status == ipr.IPR_OK, res.as_dict()
     assert err <= 1e-10
     assert abs(res.iters_fp64 - g) <= 1
+
+
+def test_householder_16384_p2_int8_slice_products(ipr):
+    """The headline schedule with every iteration product from int8 digit
+    slices (10 digits, the default): the same root as the definition."""
+    import torch
+    n, p, kappa = 16384, 2, 1e4
+    say("full size householder int8-slice products")
+    a, lam = w.householder_spd(n, kappa, seed=0)
+    A = dev(a)
+    del a
+    s = ipr.ipr_schedule_default(bulk_dtype=ipr.IPR_FP64_INT8_EMUL, scale_squarings=6,
+                                 dynamic_scaling=1, timing=1)
+    C, res = ipr.ipr_solve(A, p, 1e-10, schedule=s)
+    say("  status", res.status, "iters", res.iters_fp64, "residual", res.residual_true)
+    c = host(C)
+    del A, C
+    torch.cuda.empty_cache()
+    err = it.rel_fro(c, it.householder_root(n, kappa, 0, p))
+    say("  rel err vs definition", err)
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert res.residual_true < 1e-10
+    assert err <= 1e-10
+    assert res.lp_gemm_launches >= res.iters_fp64 and res.gemm_launches <= 10
