@@ -29,11 +29,11 @@ int8 matrix-core path computes it:
    largest (g = 2).
 
 Pins (tests/test_oracle_slices.py): the digits reproduce dyadic inputs
-exactly and other inputs within 2^(e - beta s); products of small integers
-come out exact; products of dyadic inputs with every pair kept equal the
-exact product; products of random inputs against exact rational arithmetic
-(fractions) stay within the error bound of the dropped pairs and the
-truncated digits.
+exactly and other inputs within 2^(e - beta s); level sums equal brute-force
+integer sums; products of small integers come out exact; inputs of two
+digits lose nothing but the final float64 roundings; products of random
+inputs against exact rational arithmetic (fractions) stay within the error
+bound of the dropped pairs and the digit remainders.
 """
 from __future__ import annotations
 
