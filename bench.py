@@ -11,10 +11,11 @@ Prints one JSON line. Besides the headline schedule (FP64, scaled-identity
 start whose scale is tightened by repeated squaring, dynamically scaled
 steps, triangle products) it times, outside the timed steps, the
 comparators: the same start with the plain steps of eq. (1), the
-norm-scaled identity,
-plain FP64 with full products, the eq. (3) start, low-precision bulk phases,
-FP64-accurate products from int8 digit slices, the learned start; the n = 4096 kernel matrix and the 2000-problem batch; and
-the oracle on the host cores on a bounded sample.
+norm-scaled identity, plain FP64 with full products, the eq. (3) start,
+low-precision bulk phases, FP64-accurate products from int8 digit slices,
+the learned start; the n = 4096 kernel matrix, the approximate-storage sweep
+at n = 768 and the 2000-problem batch; and the oracle on the host cores on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -191,6 +192,37 @@ def kernel_matrix_runs(ipr, torch, w, dev, tol):
                                                      torch.linalg.norm(ref))
             log(f"kernel_matrix p={p} {name}", json.dumps(row[name]))
         out[f"p{p}"] = row
+    return out
+
+
+def storage_sweep_runs(ipr, torch, w, dev, tol):
+    """The paper's approximate-storage experiment (Sections III-C, IV) at its
+    size, N = 768, p = 2, on the overlap-like kernel matrix: A and every
+    stored matrix of the iteration kept as a custom float (stored mantissa
+    bits) or fixed point (fractional bits), products in FP64. Reported: the
+    residual ||I - C^2 A||_F of the returned iterate against the float64 A,
+    the status (a coarse format ends on its floor) and the iterations."""
+    n, p = 768, 2
+    A = torch.from_numpy(w.kernel_matrix(n, seed=0)).to(dev)
+    C = torch.empty_like(A)
+    out = {"workload": "kernel_matrix n=768 (box 20, length 1, shift 1e-3, kappa 308) seed=0, "
+                       "p=2, at most 40 iterations"}
+    for fmt, code, bits_list in (("float", ipr.IPR_STORE_FLOAT, (2, 4, 7, 10, 16, 23, 30, 40, 52)),
+                                 ("fixed", ipr.IPR_STORE_FIXED, (2, 4, 8, 12, 18, 24, 32, 40))):
+        rows = {}
+        for bits in bits_list:
+            s = ipr.ipr_schedule_default(store_format=code, store_bits=bits, max_iter=40)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, raise_on=(ipr.IPR_EARG, ipr.IPR_EHIP))
+            torch.cuda.synchronize()
+            rows[str(bits)] = {"status": ipr.binding.STATUS_NAMES[r.status],
+                               "iterations": r.iters_fp64, "residual_true": r.residual_true,
+                               "seconds": time.perf_counter() - t}
+        out[fmt] = rows
+        log(f"storage sweep {fmt}", json.dumps(rows))
+    del A, C
+    torch.cuda.empty_cache()
     return out
 
 
@@ -410,6 +442,7 @@ def main():
         out["householder_16384_kappa1e2"] = householder_kappa1e2_runs(ipr, torch, w, dev, tol,
                                                                       p=p, n=n)
         out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
+        out["storage_sweep_768"] = storage_sweep_runs(ipr, torch, w, dev, tol)
         out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
 
     if not args.no_cpu:

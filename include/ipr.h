@@ -63,6 +63,14 @@ typedef enum {
                              which implies eq. (2); otherwise guard_fallback applies */
 } ipr_init;
 
+/* Approximate storage (Sections III-C and IV): how the input and every
+ * matrix the iteration stores between products are kept. */
+typedef enum {
+  IPR_STORE_NONE = 0,   /* float64 */
+  IPR_STORE_FLOAT = 1,  /* float with store_bits stored mantissa bits (1..52), unbounded exponent */
+  IPR_STORE_FIXED = 2   /* fixed point with store_bits fractional bits (1..1000), enough integer bits */
+} ipr_store_format;
+
 /* Order in which the products of eq. (1) are evaluated (Section II). */
 typedef enum {
   IPR_EVAL_COUPLED = 0,       /* M_k = C_k^p A carried along: N_k = ((p+1) I - M_k)/p,
@@ -110,6 +118,14 @@ typedef struct {
                           bulk dtype and ipr_solve (not the batched solver) */
   int emul_slices;     /* IPR_FP64_INT8_EMUL: 7-bit digits per operand, 1..12 (0: 10, which
                           reaches the FP64 result at n = 16384; see ipr_gemm_emul) */
+  int store_format;    /* ipr_store_format (default NONE). Otherwise the paper's storage-only
+                          approximation: A, C_0, M_0, N_0 and every product the iteration stores
+                          (C_k, M_k, N_k and the intermediates of N^p M) are rounded to nearest
+                          (ties to even) when written; products and epilogues compute in FP64;
+                          the final check uses the caller's A. Needs the plain coupled FP64
+                          iteration from the scaled identity (IPR_EARG otherwise); a coarse
+                          format ends on its floor (IPR_EFLOOR) */
+  int store_bits;      /* stored mantissa bits (FLOAT) or fractional bits (FIXED) */
 } ipr_schedule;
 
 typedef struct {

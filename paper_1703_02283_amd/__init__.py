@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED, IPR_INIT_USER,
     IPR_EVAL_COUPLED, IPR_EVAL_LITERAL, IPR_EVAL_NEWTON_SCHULZ,
     IPR_FP64, IPR_BF16, IPR_FP16, IPR_FP8_E4M3, IPR_FP64_INT8_EMUL, IPR_MLP_NPARAM,
+    IPR_STORE_NONE, IPR_STORE_FLOAT, IPR_STORE_FIXED,
     IprSchedule, IprResult, IprError, library_path, load,
     ipr_schedule_default, ipr_workspace_size, ipr_solve, ipr_solve_batched, ipr_gemm,
     ipr_gemm_lowp, ipr_gemm_lowp_workspace, ipr_gemm_emul, ipr_gemm_emul_workspace, ipr_norms,

@@ -15,6 +15,7 @@ IPR_OK, IPR_EARG, IPR_EMAXITER, IPR_EFLOOR, IPR_EDIVERGED, IPR_EHIP, IPR_EGUARD 
 IPR_INIT_IDENTITY, IPR_INIT_PAPER_EQ3, IPR_INIT_POLY, IPR_INIT_LEARNED, IPR_INIT_USER = range(5)
 IPR_EVAL_COUPLED, IPR_EVAL_LITERAL, IPR_EVAL_NEWTON_SCHULZ = range(3)
 IPR_FP64, IPR_BF16, IPR_FP16, IPR_FP8_E4M3, IPR_FP64_INT8_EMUL = range(5)
+IPR_STORE_NONE, IPR_STORE_FLOAT, IPR_STORE_FIXED = range(3)
 IPR_MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3
 STATUS_NAMES = {0: "OK", 1: "EARG", 2: "EMAXITER", 3: "EFLOOR", 4: "EDIVERGED", 5: "EHIP",
                 6: "EGUARD"}
@@ -27,7 +28,8 @@ class IprSchedule(ct.Structure):
                 ("poly", ct.c_double * 3), ("mlp_params", ct.c_void_p), ("timing", ct.c_int),
                 ("tile", ct.c_int), ("scale_squarings", ct.c_int),
                 ("dynamic_scaling", ct.c_int), ("evaluation", ct.c_int),
-                ("emul_slices", ct.c_int)]
+                ("emul_slices", ct.c_int), ("store_format", ct.c_int),
+                ("store_bits", ct.c_int)]
 
 
 class IprResult(ct.Structure):

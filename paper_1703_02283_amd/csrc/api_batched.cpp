@@ -219,6 +219,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
     return fail(IPR_EARG, "ipr_solve_batched: bulk dtype must be FP64 or BF16");
   if (s.evaluation != IPR_EVAL_COUPLED)
     return fail(IPR_EARG, "ipr_solve_batched: only the coupled order is supported");
+  if (s.store_format != IPR_STORE_NONE)
+    return fail(IPR_EARG, "ipr_solve_batched: approximate storage is an ipr_solve option");
   if (s.tile != 0 && !valid_tile(s.tile))
     return fail(IPR_EARG, "ipr_solve_batched: tile must be 0, 32 or 64");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve_batched: max_iter < 0");

@@ -2,6 +2,8 @@
 // identity start, the Frobenius-norm reduction and small elementwise maps.
 // All reductions run in a fixed order, so their results are bitwise
 // reproducible from run to run.
+#include <algorithm>
+
 #include "ipr_internal.h"
 
 namespace ipr {
@@ -227,6 +229,19 @@ hipError_t norms_1_inf(const double* A, int n, double* scratch, double* out, hip
   hipLaunchKernelGGL(col_abs_finish, dim3((n + NT - 1) / NT), dim3(NT), 0, stream, part, n, strips,
                      cols);
   hipLaunchKernelGGL(max2, dim3(1), dim3(1024), 0, stream, cols, rows, n, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(NT) void round_kernel(double* __restrict__ X, size_t count, int fmt,
+                                                   int bits) {
+  for (size_t i = blockIdx.x * (size_t)NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT)
+    X[i] = round_store(X[i], fmt, bits);
+}
+
+hipError_t round_matrix(double* X, size_t count, int fmt, int bits, hipStream_t stream) {
+  const size_t blocks = std::min<size_t>((count + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(round_kernel, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(NT), 0, stream,
+                     X, count, fmt, bits);
   return hipGetLastError();
 }
 

@@ -13,6 +13,9 @@ namespace ipr {
 //   D[i,j] = out                                   (when D != nullptr)
 //   S[i,j] = (s_init ? sa*(i==j) + sb*Y[i,j] : S[i,j]) + sc*out   (when S != nullptr)
 //   partial[tile] = sum of (out - pd*(i==j))^2 over the tile (when partial != nullptr)
+// With rfmt != 0, out and the S value are rounded as stored values
+// (round_store) before they are written and before S and the partial sums
+// use out.
 // In triangle mode only tiles with row-block <= column-block are computed;
 // every element with i <= j is written to (i, j) and (j, i), and the partial
 // sums count off-diagonal elements twice, so they are sums over the full matrix.
@@ -28,7 +31,25 @@ struct Epilogue {
   int s_init = 0;
   double* partial = nullptr;
   double pd = 0.0;
+  int rfmt = 0;    // 0: none, 1: float with rbits stored mantissa bits, 2: fixed point, rbits fractional bits
+  int rbits = 0;
 };
+
+// A value as the approximate storage of Sections III-C and IV keeps it: a
+// float with `bits` stored mantissa bits and an unbounded exponent (fmt 1),
+// or fixed point with `bits` fractional bits and enough integer bits (fmt 2);
+// round to nearest, ties to even. Zero, Inf and NaN pass unchanged.
+__host__ __device__ inline double round_store(double v, int fmt, int bits) {
+  if (fmt == 1) {
+    if (v == 0.0 || !(fabs(v) <= 1.79769313486231570815e308)) return v;
+    int e;
+    (void)frexp(v, &e);              // v = f 2^e, 0.5 <= |f| < 1: leading bit 2^(e-1)
+    const int sh = e - 1 - bits;     // weight of the last stored bit
+    return ldexp(rint(ldexp(v, -sh)), sh);
+  }
+  if (fmt == 2) return ldexp(rint(ldexp(v, bits)), -bits);
+  return v;
+}
 
 // Number of per-tile partial slots a product of order n writes.
 int gemm_partial_slots(int n, int tri);
@@ -57,6 +78,9 @@ hipError_t affine(const double* X, int n, double a, double b, double* Y,
                   hipStream_t stream);
 
 hipError_t copy(const double* X, size_t count, double* Y, hipStream_t stream);
+
+// X[i] = round_store(X[i], fmt, bits) for i < count.
+hipError_t round_matrix(double* X, size_t count, int fmt, int bits, hipStream_t stream);
 
 // Y = a0 I + a1 A + a2 G (G may be null).
 hipError_t lincomb(const double* A, const double* G, int n, double a0, double a1, double a2,

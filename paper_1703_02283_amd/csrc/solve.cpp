@@ -122,6 +122,7 @@ struct Work {
   unsigned long long* cm;
   double* slP;
   double* slS;
+  double* Ar;   // approximate storage: A as stored
 };
 
 // digits per operand of the int8-slice products (0 when the dtype does not use them)
@@ -132,7 +133,8 @@ int emul_digits(const ipr_schedule& s) {
 
 int n_mats(int p) { return p == 1 ? 5 : (p == 2 ? 6 : NMAT); }
 
-size_t carve(int n, int p, int dtype, int slices, Work* w, void* base, size_t cap, bool* ok) {
+size_t carve(int n, int p, int dtype, int slices, bool store, Work* w, void* base, size_t cap,
+             bool* ok) {
   Carver c(base, cap);
   const size_t nn = (size_t)n * n;
   const int nm = n_mats(p);
@@ -155,6 +157,7 @@ size_t carve(int n, int p, int dtype, int slices, Work* w, void* base, size_t ca
   w->cm = emul ? c.take<unsigned long long>(n) : nullptr;
   w->slP = emul ? c.take<double>(nn) : nullptr;
   w->slS = emul ? c.take<double>(nn) : nullptr;
+  w->Ar = store ? c.take<double>(nn) : nullptr;
   *ok = c.ok();
   return c.used;
 }
@@ -184,6 +187,7 @@ struct Prod {
   hipStream_t st;
   int lowp_dtype = 0;  // 0: FP64 products
   int emul = 0;        // > 0: int8-slice products with this many digits
+  int rfmt = 0, rbits = 0;  // approximate storage of the iteration's products (round_store)
   Work* w;
   int gemms = 0;
   bool timing = false;
@@ -222,16 +226,23 @@ struct Prod {
   }
   // a product in FP64 whatever the phase
   hipError_t f64(const double* L, const double* R, int tri, const Epilogue& e) {
-    const int keep = lowp_dtype, keep_e = emul;
+    const int keep = lowp_dtype, keep_e = emul, keep_r = rfmt;
     lowp_dtype = 0;
     emul = 0;
+    rfmt = 0;
     hipError_t err = (*this)(L, R, tri, e);
     lowp_dtype = keep;
     emul = keep_e;
+    rfmt = keep_r;
     return err;
   }
-  hipError_t operator()(const double* L, const double* R, int tri, const Epilogue& e) {
+  hipError_t operator()(const double* L, const double* R, int tri, const Epilogue& e_in) {
     hipError_t err = hipSuccess;
+    Epilogue e = e_in;
+    if (rfmt) {
+      e.rfmt = rfmt;
+      e.rbits = rbits;
+    }
     ++gemms;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto start = [&]() -> hipError_t {
@@ -296,7 +307,8 @@ struct Prod {
   } while (0)
 
 struct Solver {
-  const double* A;
+  const double* A;      // the A the iteration multiplies by (as stored)
+  const double* Atrue;  // the caller's A: the final check uses it
   int n, p, tri;
   hipStream_t st;
   Work w;
@@ -461,7 +473,7 @@ struct Solver {
     e.alpha = -1.0;
     e.gamma = 1.0;
     e.partial = w.partial;
-    TRY(prod.f64(P, A, 0, e));
+    TRY(prod.f64(P, Atrue, 0, e));
     TRY(reduce_fro(w.partial, gemm_partial_slots(n, 0), w.scal + 9, st));
     return read_scalars(w.scal + 9, 1, tau, st);
   }
@@ -551,7 +563,8 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
   bool ok;
   const int dt = s ? s->bulk_dtype : IPR_FP64;
   const int sl = s ? emul_digits(*s) : 0;
-  const size_t single = carve(n_max, p_max, dt, sl, &w, nullptr, (size_t)-1, &ok) + 256;
+  const bool store = s && s->store_format != IPR_STORE_NONE;
+  const size_t single = carve(n_max, p_max, dt, sl, store, &w, nullptr, (size_t)-1, &ok) + 256;
   return std::max(single, batched_workspace_bytes(n_max, batch));
 }
 
@@ -615,16 +628,30 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     if (n > slice_max_n())
       return fail(IPR_EARG, "ipr_solve: int8-slice products need n <= %d", slice_max_n());
   }
+  const bool store = s.store_format != IPR_STORE_NONE;
+  if (s.store_format < IPR_STORE_NONE || s.store_format > IPR_STORE_FIXED)
+    return fail(IPR_EARG, "ipr_solve: unknown store_format %d", s.store_format);
+  if (store) {
+    if (s.store_format == IPR_STORE_FLOAT && (s.store_bits < 1 || s.store_bits > 52))
+      return fail(IPR_EARG, "ipr_solve: store_bits must be 1..52 stored mantissa bits");
+    if (s.store_format == IPR_STORE_FIXED && (s.store_bits < 1 || s.store_bits > 1000))
+      return fail(IPR_EARG, "ipr_solve: store_bits must be 1..1000 fractional bits");
+    if (s.init != IPR_INIT_IDENTITY || s.evaluation != IPR_EVAL_COUPLED ||
+        s.bulk_dtype != IPR_FP64 || s.scale_squarings || s.dynamic_scaling)
+      return fail(IPR_EARG, "ipr_solve: approximate storage runs the plain coupled iteration "
+                  "from the scaled identity in FP64 (no squarings, no scaled steps)");
+  }
   if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
     return fail(IPR_EARG, "ipr_solve: the learned start needs schedule.mlp_params");
 
   Solver sv;
   bool ok;
-  carve(n, p, s.bulk_dtype, slices, &sv.w, dWork, work_bytes, &ok);
+  carve(n, p, s.bulk_dtype, slices, store, &sv.w, dWork, work_bytes, &ok);
   if (!ok)
     return fail(IPR_EARG, "ipr_solve: workspace too small (%zu bytes, need %zu)", work_bytes,
                 ipr_workspace_size(n, p, 1, sched));
   sv.A = dA;
+  sv.Atrue = dA;
   sv.n = n;
   sv.p = p;
   sv.tri = s.triangle ? 1 : 0;
@@ -794,8 +821,21 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   } else if (b[1] == 0.0 && b[2] == 0.0) {
     // scaled identity c I, c = b0 sc^{-1/p}: M_0 = c^p A elementwise
     const double c = b[0] * root;
-    HIP_TRY(init_identity(dA, n, p, c, std::pow(b[0], (double)p) / sc, sv.C(), sv.M(),
+    if (store) {
+      // approximate storage (Sections III-C, IV): the iteration works on A
+      // as stored, and C_0, M_0, N_0 are stored the same way
+      HIP_TRY(copy(dA, nn, w.Ar, stream));
+      HIP_TRY(round_matrix(w.Ar, nn, s.store_format, s.store_bits, stream));
+      sv.A = w.Ar;
+    }
+    HIP_TRY(init_identity(sv.A, n, p, c, std::pow(b[0], (double)p) / sc, sv.C(), sv.M(),
                           sv.Nb[sv.ni], w.partial, stream));
+    if (store) {
+      for (double* X : {sv.C(), sv.M(), sv.Nb[sv.ni]})
+        HIP_TRY(round_matrix(X, nn, s.store_format, s.store_bits, stream));
+      sv.prod.rfmt = s.store_format;
+      sv.prod.rbits = s.store_bits;
+    }
     sv.slots = n;
     if (int rc = sv.reduce()) return rc;
   } else {
@@ -1061,7 +1101,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     // feed the convergence test, and the check of the true residual that
     // follows it anyway replaces that test. If the check fails (rounding
     // floor), M is recomputed from C_{k+1} and the iteration goes on.
-    const bool clean = !ns && (!lowp || lp_restart);
+    const bool clean = !ns && (!lowp || lp_restart) && !store;
     if (clean && s.verify && !short_failed && sv.mu_cur == 1.0 && rho < 0.5 &&
         (p + 1.0) / (2.0 * p) * rho * rho < tol && k < kmax) {
       if (int rc = sv.step(false, false)) return rc;
