@@ -42,9 +42,7 @@ struct Epilogue {
 __host__ __device__ inline double round_store(double v, int fmt, int bits) {
   if (fmt == 1) {
     if (v == 0.0 || !(fabs(v) <= 1.79769313486231570815e308)) return v;
-    int e;
-    (void)frexp(v, &e);              // v = f 2^e, 0.5 <= |f| < 1: leading bit 2^(e-1)
-    const int sh = e - 1 - bits;     // weight of the last stored bit
+    const int sh = ilogb(v) - bits;  // leading bit 2^ilogb(v): weight of the last stored bit
     return ldexp(rint(ldexp(v, -sh)), sh);
   }
   if (fmt == 2) return ldexp(rint(ldexp(v, bits)), -bits);

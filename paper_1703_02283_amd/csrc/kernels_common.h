@@ -56,7 +56,9 @@ __device__ __forceinline__ bool tile_of(int lw, const Grid& gr, int tri, int* bi
 }
 
 // Applies the epilogue to element (i, j) whose product value is acc; adds its
-// contribution to the Frobenius partial sum.
+// contribution to the Frobenius partial sum. kStore = false compiles out the
+// approximate-storage rounding (for kernels whose callers never ask for it).
+template <bool kStore = true>
 __device__ __forceinline__ void epilogue_element(const Epilogue& e, int n, int tri, int i, int j,
                                                  double acc, double& psum) {
   if (i >= n || j >= n) return;
@@ -67,7 +69,7 @@ __device__ __forceinline__ void epilogue_element(const Epilogue& e, int n, int t
   double v = e.alpha * acc;
   if (e.X) v += e.beta * e.X[ij];
   if (i == j) v += e.gamma;
-  if (e.rfmt) v = round_store(v, e.rfmt, e.rbits);
+  if (kStore && e.rfmt) v = round_store(v, e.rfmt, e.rbits);
   if (e.D) {
     e.D[ij] = v;
     if (mirror) e.D[ji] = v;
@@ -75,7 +77,7 @@ __device__ __forceinline__ void epilogue_element(const Epilogue& e, int n, int t
   if (e.S) {
     double s = e.s_init ? ((i == j ? e.sa : 0.0) + (e.Y ? e.sb * e.Y[ij] : 0.0)) : e.S[ij];
     s += e.sc * v;
-    if (e.rfmt) s = round_store(s, e.rfmt, e.rbits);
+    if (kStore && e.rfmt) s = round_store(s, e.rfmt, e.rbits);
     e.S[ij] = s;
     if (mirror) e.S[ji] = s;
   }

@@ -208,7 +208,7 @@ __device__ __forceinline__ void slice_element(const SliceArgs& sa, const int* EL
     sa.S[ij] = term;
     return;
   }
-  epilogue_element(e, n, tri, i, j, term, psum);
+  epilogue_element<false>(e, n, tri, i, j, term, psum);
 }
 
 // D = L^T R from k-contiguous codes Lt (row i), Rt (row j), order np (a
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
         const int i = i0 + (q >> 5) * 128 + h * 32 + (q & 31);
         const int j = j0 + tid;
         const double post = post_sh[(q >> 5) * 2 + (tid >> 7)];  // the owning wave's
-        epilogue_element(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
+        epilogue_element<false>(e, n, tri, i, j, (double)*stg_at(q, tid) * post, psum);
       }
     }
   }

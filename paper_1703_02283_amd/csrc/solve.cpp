@@ -239,7 +239,8 @@ struct Prod {
   hipError_t operator()(const double* L, const double* R, int tri, const Epilogue& e_in) {
     hipError_t err = hipSuccess;
     Epilogue e = e_in;
-    if (rfmt) {
+    if (rfmt && !lowp_dtype && !emul) {  // (the FP64 kernel's epilogue rounds; solve() allows
+                                          // approximate storage with FP64 products only)
       e.rfmt = rfmt;
       e.rbits = rbits;
     }
