@@ -197,31 +197,41 @@ def kernel_matrix_runs(ipr, torch, w, dev, tol):
 
 def storage_sweep_runs(ipr, torch, w, dev, tol):
     """The paper's approximate-storage experiment (Sections III-C, IV) at its
-    size, N = 768, p = 2, on the overlap-like kernel matrix: A and every
+    size, N = 768, p = 2, on the overlap-like kernel matrix and on a
+    well-conditioned (kappa = 10) matrix: A and every
     stored matrix of the iteration kept as a custom float (stored mantissa
     bits) or fixed point (fractional bits), products in FP64. Reported: the
     residual ||I - C^2 A||_F of the returned iterate against the float64 A,
     the status (a coarse format ends on its floor) and the iterations."""
     n, p = 768, 2
-    A = torch.from_numpy(w.kernel_matrix(n, seed=0)).to(dev)
-    C = torch.empty_like(A)
-    out = {"workload": "kernel_matrix n=768 (box 20, length 1, shift 1e-3, kappa 308) seed=0, "
-                       "p=2, at most 40 iterations"}
-    for fmt, code, bits_list in (("float", ipr.IPR_STORE_FLOAT, (2, 4, 7, 10, 16, 23, 30, 40, 52)),
-                                 ("fixed", ipr.IPR_STORE_FIXED, (2, 4, 8, 12, 18, 24, 32, 40))):
-        rows = {}
-        for bits in bits_list:
-            s = ipr.ipr_schedule_default(store_format=code, store_bits=bits, max_iter=40)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C, raise_on=(ipr.IPR_EARG, ipr.IPR_EHIP))
-            torch.cuda.synchronize()
-            rows[str(bits)] = {"status": ipr.binding.STATUS_NAMES[r.status],
-                               "iterations": r.iters_fp64, "residual_true": r.residual_true,
-                               "seconds": time.perf_counter() - t}
-        out[fmt] = rows
-        log(f"storage sweep {fmt}", json.dumps(rows))
-    del A, C
+    out = {"note": "p=2, at most 40 iterations; residual_true = ||I - C^2 A||_F of the returned "
+                   "iterate against the float64 A"}
+    inputs = (("kernel_matrix_768", "kernel_matrix n=768 (box 20, length 1, shift 1e-3, "
+                                    "kappa 308) seed=0", w.kernel_matrix(n, seed=0)),
+              ("spd_kappa10_768", "spd_log_spectrum n=768 kappa=10 seed=0",
+               w.spd_log_spectrum(n, 10.0, seed=0)[0]))
+    for key, desc, a in inputs:
+        A = torch.from_numpy(a).to(dev)
+        C = torch.empty_like(A)
+        sec = {"workload": desc}
+        for fmt, code, bits_list in (("float", ipr.IPR_STORE_FLOAT,
+                                      (2, 4, 7, 10, 16, 23, 30, 40, 52)),
+                                     ("fixed", ipr.IPR_STORE_FIXED, (2, 4, 8, 12, 18, 24, 32, 40))):
+            rows = {}
+            for bits in bits_list:
+                s = ipr.ipr_schedule_default(store_format=code, store_bits=bits, max_iter=40)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, r = ipr.ipr_solve(A, p, tol, schedule=s, out=C,
+                                     raise_on=(ipr.IPR_EARG, ipr.IPR_EHIP))
+                torch.cuda.synchronize()
+                rows[str(bits)] = {"status": ipr.binding.STATUS_NAMES[r.status],
+                                   "iterations": r.iters_fp64, "residual_true": r.residual_true,
+                                   "seconds": time.perf_counter() - t}
+            sec[fmt] = rows
+            log(f"storage sweep {key} {fmt}", json.dumps(rows))
+        out[key] = sec
+        del A, C
     torch.cuda.empty_cache()
     return out
 
