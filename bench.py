@@ -232,6 +232,27 @@ def storage_sweep_runs(ipr, torch, w, dev, tol):
             log(f"storage sweep {key} {fmt}", json.dumps(rows))
         out[key] = sec
         del A, C
+    # sizes (N = 768 2^k at constant point density, as for larger systems) and
+    # powers p, for a few formats each (the paper's size and p comparisons)
+    def one(A, pp, code, bits):
+        s = ipr.ipr_schedule_default(store_format=code, store_bits=bits, max_iter=40)
+        _, r = ipr.ipr_solve(A, pp, tol, schedule=s, raise_on=(ipr.IPR_EARG, ipr.IPR_EHIP))
+        return {"status": ipr.binding.STATUS_NAMES[r.status], "iterations": r.iters_fp64,
+                "residual_true": r.residual_true}
+    fmts = (("float", ipr.IPR_STORE_FLOAT, (10, 16, 23)), ("fixed", ipr.IPR_STORE_FIXED, (12, 18, 24)))
+    sizes = {}
+    for nn in (768, 1536, 3072, 6144):
+        A = torch.from_numpy(w.kernel_matrix(nn, seed=0, box=20.0 * (nn / 768) ** (1 / 3))).to(dev)
+        sizes[str(nn)] = {f"{f}{b}": one(A, 2, code, b) for f, code, bl in fmts for b in bl}
+        del A
+    out["sizes_p2_kernel_matrix_constant_density"] = sizes
+    log("storage sweep sizes", json.dumps(sizes))
+    A = torch.from_numpy(w.kernel_matrix(n, seed=0)).to(dev)
+    powers = {str(pp): {f"fixed{b}": one(A, pp, ipr.IPR_STORE_FIXED, b) for b in (12, 18, 24, 32)}
+              for pp in (1, 2, 3, 4)}
+    out["powers_kernel_matrix_768_fixed"] = powers
+    log("storage sweep powers", json.dumps(powers))
+    del A
     torch.cuda.empty_cache()
     return out
 
