@@ -68,7 +68,7 @@ typedef enum {
 typedef enum {
   IPR_STORE_NONE = 0,   /* float64 */
   IPR_STORE_FLOAT = 1,  /* float with store_bits stored mantissa bits (1..52), unbounded exponent */
-  IPR_STORE_FIXED = 2   /* fixed point with store_bits fractional bits (1..1000), enough integer bits */
+  IPR_STORE_FIXED = 2   /* fixed point with store_bits fractional bits (1..64), enough integer bits */
 } ipr_store_format;
 
 /* Order in which the products of eq. (1) are evaluated (Section II). */

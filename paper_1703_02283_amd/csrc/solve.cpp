@@ -635,8 +635,9 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   if (store) {
     if (s.store_format == IPR_STORE_FLOAT && (s.store_bits < 1 || s.store_bits > 52))
       return fail(IPR_EARG, "ipr_solve: store_bits must be 1..52 stored mantissa bits");
-    if (s.store_format == IPR_STORE_FIXED && (s.store_bits < 1 || s.store_bits > 1000))
-      return fail(IPR_EARG, "ipr_solve: store_bits must be 1..1000 fractional bits");
+    // (2^bits |x| must stay finite for every stored value)
+    if (s.store_format == IPR_STORE_FIXED && (s.store_bits < 1 || s.store_bits > 64))
+      return fail(IPR_EARG, "ipr_solve: store_bits must be 1..64 fractional bits");
     if (s.init != IPR_INIT_IDENTITY || s.evaluation != IPR_EVAL_COUPLED ||
         s.bulk_dtype != IPR_FP64 || s.scale_squarings || s.dynamic_scaling)
       return fail(IPR_EARG, "ipr_solve: approximate storage runs the plain coupled iteration "

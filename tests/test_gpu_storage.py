@@ -69,7 +69,7 @@ def test_storage_argument_errors(ipr):
     say("storage errors")
     a = dev(np.eye(64) * 2.0)
     for kw in ({"store_format": 1, "store_bits": 0}, {"store_format": 1, "store_bits": 53},
-               {"store_format": 3, "store_bits": 8},
+               {"store_format": 3, "store_bits": 8}, {"store_format": 2, "store_bits": 65},
                {"store_format": 1, "store_bits": 10, "dynamic_scaling": 1},
                {"store_format": 1, "store_bits": 10, "scale_squarings": 2},
                {"store_format": 2, "store_bits": 10, "bulk_dtype": 1}):
