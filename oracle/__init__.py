@@ -26,6 +26,10 @@ Parity pins (tests marked "not gpu" check each of these):
                          paper's eq. (3) start.
   * int8-slice product - against exact integer and rational arithmetic
                          (brute force on tiny inputs) and its error bound.
+  * approximate storage - against the scalar recursion on diagonal A, the
+                         stored-bit floors and the behaviour Section IV-C reports.
+  * Loewdin transform  - against scipy's generalised eigenvalues and closed
+                         forms.
 Parity unpinned: none of the functions above lacks a pin. The accuracy the
 low-precision bulk phase reaches end to end has no value in the paper to
 compare with (its figures are not available); it is checked against this

@@ -97,6 +97,29 @@ def kernel_matrix(n: int = 4096, seed: int = 0, box: float = 20.0,
     return 0.5 * (a + a.T)
 
 
+def overlap_and_hamiltonian(n: int = 1024, seed: int = 0, box: float = 20.0,
+                            shift: float = 1e-3):
+    """(S, H) for n s-type Gaussians (exponent 1/2, unit length) at points
+    uniform in [0, box]^3: S = kernel_matrix(n, seed, box, 1, shift), and a
+    Hamiltonian-like H with the same decay: the kinetic-energy form of
+    Gaussians, S_ij (3 - d_ij^2 / 2) / 4, plus a potential -exp(-|x_i - c|^2 / 50)
+    on the diagonal (c the box centre). Same draw order as kernel_matrix (the
+    points); H is exactly symmetric."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, box, (n, 3))
+    sq = np.sum(x * x, axis=1)
+    d2 = sq[:, None] + sq[None, :] - 2.0 * (x @ x.T)
+    np.maximum(d2, 0.0, out=d2)
+    np.fill_diagonal(d2, 0.0)
+    d2 = 0.5 * (d2 + d2.T)
+    g = np.exp(-d2 / 2.0)
+    s = g + shift * np.eye(n)
+    h = g * (3.0 - d2 / 2.0) / 4.0
+    c = np.full(3, box / 2.0)
+    h -= np.diag(np.exp(-np.sum((x - c) ** 2, axis=1) / 50.0))
+    return 0.5 * (s + s.T), 0.5 * (h + h.T)
+
+
 def householder_factors(n: int, kappa: float, seed: int = 0, nrefl: int = 64):
     """Spectrum and compact-WY form of H = H_1 H_2 ... H_k, H_i = I - 2 v_i v_i^T / |v_i|^2.
 
