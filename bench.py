@@ -14,8 +14,8 @@ comparators: the same start with the plain steps of eq. (1), the
 norm-scaled identity, plain FP64 with full products, the eq. (3) start,
 low-precision bulk phases, FP64-accurate products from int8 digit slices,
 the learned start; the n = 4096 kernel matrix, the approximate-storage sweep
-at n = 768 and the 2000-problem batch; and the oracle on the host cores on a
-bounded sample.
+at n = 768, the Loewdin transform at n = 4096 and the 2000-problem batch; and
+the oracle on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -257,6 +257,34 @@ def storage_sweep_runs(ipr, torch, w, dev, tol):
     return out
 
 
+def lowdin_runs(ipr, torch, w, dev, tol):
+    """The step after the inverse square root in the paper's application:
+    S^{-1/2} H S^{-1/2} for the n = 4096 overlap matrix and a Hamiltonian-like
+    matrix of the same Gaussian basis (ipr_lowdin: the p = 2 solve plus two
+    FP64 products)."""
+    n = 4096
+    s, h = w.overlap_and_hamiltonian(n, seed=0)
+    S, H = torch.from_numpy(s).to(dev), torch.from_numpy(h).to(dev)
+    del s, h
+    out = {"workload": "overlap_and_hamiltonian n=4096 (box 20) seed=0, tol 1e-10"}
+    for name, kw in (("fp64_default", {}),
+                     ("fp64_power_scale_scaled_steps", dict(scale_squarings=6, dynamic_scaling=1))):
+        sch = ipr.ipr_schedule_default(timing=1, **kw)
+        ipr.ipr_lowdin(S, H, tol, schedule=sch)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        X, Ht, r = ipr.ipr_lowdin(S, H, tol, schedule=sch)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t,
+                     "status": ipr.binding.STATUS_NAMES[r.status], "iterations": r.iters_fp64,
+                     "residual_true": r.residual_true,
+                     "asymmetry": float((Ht - Ht.T).abs().max())}
+        log(f"lowdin {name}", json.dumps(out[name]))
+    del S, H
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_runs(ipr, torch, w, dev, tol, reps=3):
     """2000 independent problems, n ~ U{32..512}, p in {1, 2, 4}, kappa
     log-uniform in [10, 1e5]: one captured launch per call."""
@@ -474,6 +502,7 @@ def main():
                                                                       p=p, n=n)
         out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
         out["storage_sweep_768"] = storage_sweep_runs(ipr, torch, w, dev, tol)
+        out["lowdin_4096"] = lowdin_runs(ipr, torch, w, dev, tol)
         out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
 
     if not args.no_cpu:

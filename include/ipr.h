@@ -251,6 +251,22 @@ int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int sli
                   void* dWork, size_t work_bytes, hipStream_t stream);
 size_t ipr_gemm_emul_workspace(int n, int slices);
 
+/* Loewdin orthogonalisation, the step after the inverse square root in the
+ * paper's application (Section IV-A: the generalised eigenproblem
+ * H c = e S c of a non-orthogonal basis in standard form): dX = S^{-1/2} by
+ * ipr_solve (p = 2, schedule s, tolerance tol; `out` is its result), then
+ * dHout = X H X from two FP64 products (H X in full, then X (H X) as one
+ * mirrored triangle). The eigenvalues of Hout are those of (H, S); an
+ * eigenvector y of Hout gives c = X y. S and H: n x n float64, symmetric,
+ * row-major, device; dX, dHout: n x n device outputs that alias neither input
+ * nor each other. dWork >= ipr_lowdin_workspace(n, s) bytes (device). Returns
+ * the solve's status (dHout is written only when it is IPR_OK), IPR_EARG for
+ * bad arguments, IPR_EHIP for HIP failures. Stream-ordered on `stream`. */
+int ipr_lowdin(const double* dS, const double* dH, double* dX, double* dHout, int n, double tol,
+               const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
+               hipStream_t stream);
+size_t ipr_lowdin_workspace(int n, const ipr_schedule* s);
+
 /* ||A||_1 and ||A||_inf (eq. (3)) into host out[0], out[1]. dWork >= n*(n/256+2)*8 bytes. */
 int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
               hipStream_t stream);

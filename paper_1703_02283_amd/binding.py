@@ -83,6 +83,10 @@ _SIGS = {
     "ipr_gemm_emul": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
                                  ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ipr_gemm_emul_workspace": (ct.c_size_t, [ct.c_int, ct.c_int]),
+    "ipr_lowdin": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
+                              ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                              ct.c_void_p]),
+    "ipr_lowdin_workspace": (ct.c_size_t, [ct.c_int, ct.c_void_p]),
     "ipr_norms": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                              ct.c_void_p]),
     "ipr_features": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
@@ -208,6 +212,25 @@ def ipr_solve(A, p, tol, schedule=None, out=None, workspace=None, stream=None,
     if rc in raise_on:
         raise IprError(rc, ipr_last_error())
     return C, res
+
+
+def ipr_lowdin(S, H, tol, schedule=None, out_x=None, out_h=None, workspace=None, stream=None,
+               raise_on=(IPR_EARG, IPR_EHIP, IPR_EGUARD)):
+    """(X, X H X, IprResult) with X = S^{-1/2} (see include/ipr.h)."""
+    _need(S, torch.float64, name="S")
+    n = S.shape[0]
+    _need(H, torch.float64, (n, n), "H")
+    sch = schedule if schedule is not None else ipr_schedule_default()
+    X = out_x if out_x is not None else torch.empty_like(S)
+    Ht = out_h if out_h is not None else torch.empty_like(S)
+    ws = workspace if workspace is not None else _workspace(
+        int(_fn("ipr_lowdin_workspace")(n, ct.byref(sch))), S.device)
+    res = IprResult()
+    rc = _fn("ipr_lowdin")(_ptr(S), _ptr(H), _ptr(X), _ptr(Ht), n, tol, ct.byref(sch),
+                           ct.byref(res), _ptr(ws), ws.numel(), _stream(stream))
+    if rc in raise_on:
+        raise IprError(rc, ipr_last_error())
+    return X, Ht, res
 
 
 def ipr_solve_batched(A_packed, offsets, ns, ps, tol, schedule=None, out=None,

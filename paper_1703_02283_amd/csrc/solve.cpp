@@ -569,6 +569,35 @@ size_t ipr_workspace_size(int n_max, int p_max, int batch, const ipr_schedule* s
   return std::max(single, batched_workspace_bytes(n_max, batch));
 }
 
+size_t ipr_lowdin_workspace(int n, const ipr_schedule* s) {
+  if (n < 1) return 0;
+  return std::max(ipr_workspace_size(n, 2, 1, s), (size_t)n * n * sizeof(double) + 256);
+}
+
+int ipr_lowdin(const double* dS, const double* dH, double* dX, double* dHout, int n, double tol,
+               const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
+               hipStream_t stream) {
+  g_last_error.clear();
+  if (!dS || !dH || !dX || !dHout || !dWork || n < 1)
+    return fail(IPR_EARG, "ipr_lowdin: bad argument");
+  if (dHout == dS || dHout == dH || dHout == dX || dX == dH)
+    return fail(IPR_EARG, "ipr_lowdin: outputs must not alias the inputs or each other");
+  if (work_bytes < ipr_lowdin_workspace(n, s))
+    return fail(IPR_EARG, "ipr_lowdin: workspace too small (%zu bytes, need %zu)", work_bytes,
+                ipr_lowdin_workspace(n, s));
+  if (int rc = ipr_solve(dS, dX, n, 2, tol, s, out, dWork, work_bytes, stream)) return rc;
+  // the solve is done with its workspace: its first n^2 doubles hold H X
+  Carver c(dWork, work_bytes);
+  double* T = c.take<double>((size_t)n * n);
+  Epilogue e1;
+  e1.D = T;
+  HIP_TRY(gemm_f64(dH, dX, n, 0, e1, stream));     // (H^T X = H X, H symmetric)
+  Epilogue e2;
+  e2.D = dHout;
+  HIP_TRY(gemm_f64(T, dX, n, 1, e2, stream));      // (H X)^T X = X H X: symmetric, one triangle
+  return IPR_OK;
+}
+
 int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_bytes,
               hipStream_t stream) {
   g_last_error.clear();
