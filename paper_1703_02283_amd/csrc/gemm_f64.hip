@@ -88,9 +88,14 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  // Workgroup w runs on XCD w % 8; each XCD takes a contiguous run of the
+  // logical order (in triangle mode of the tiles that exist, so that every
+  // XCD gets the same number).
   const int lw = logical_wg();
   int bi, bj;
-  if (!tile_of(lw, gr, tri, &bi, &bj)) {
+  const bool ok = tri ? lw < gr.nreal && tri_tile_of(lw, gr, &bi, &bj)
+                      : tile_of(lw, gr, 0, &bi, &bj);
+  if (!ok) {
     if (e.partial && tid == 0) e.partial[lw] = 0.0;
     return;
   }
@@ -324,14 +329,19 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
 
 }  // namespace
 
-int gemm_partial_slots(int n, int tri) { return make_grid(n, tri, BM).nwg; }
+namespace {
+int launch_wgs(const Grid& gr, int tri) { return tri ? (gr.nreal + 7) / 8 * 8 : gr.nwg; }
+}  // namespace
+
+int gemm_partial_slots(int n, int tri) { return launch_wgs(make_grid(n, tri, BM), tri); }
 
 hipError_t gemm_f64(const double* L, const double* R, int n, int tri, const Epilogue& e,
                     hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   if (!L || !R) return hipErrorInvalidValue;  // never launch on a missing operand
   Grid gr = make_grid(n, tri, BM);
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3(gr.nwg), dim3(NT), 0, stream, L, R, n, gr, tri, e);
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3(launch_wgs(gr, tri)), dim3(NT), 0, stream, L, R, n, gr,
+                     tri, e);
   return hipGetLastError();
 }
 
