@@ -78,9 +78,25 @@ __device__ __forceinline__ void wg_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// Triangle mode with a split tail: each XCD's run of q tiles is cut into
+// qmain = a multiple of its CU count (whole rounds) and tailq leftover tiles,
+// which would otherwise run as one round on tailq of its CUs. The leftover
+// tiles are instead split along k into kparts ranges of klen, one workgroup
+// each, whose raw sums go to `part`; tail_reduce_kernel adds them and applies
+// the epilogue. q = 0: no split (the usual logical order).
+struct TailArgs {
+  int q;        // tiles per XCD run
+  int qmain;    // tiles per run computed whole
+  int tailq;    // tiles per run split along k
+  int kparts;   // k ranges per split tile
+  int klen;     // k per range (a multiple of 64)
+  double* part; // 8 tailq kparts tiles of BM x BM sums
+};
+
+template <bool kSplit>
 __global__ __launch_bounds__(NT, 1)
 void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R, int n,
-                     Grid gr, int tri, Epilogue e) {
+                     Grid gr, int tri, Epilogue e, TailArgs ta) {
   __shared__ double Ls[2][BK][LDP];
   __shared__ double Rs[2][BK][LDP];
   __shared__ double red[NT / 64];
@@ -91,12 +107,19 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   // Workgroup w runs on XCD w % 8; each XCD takes a contiguous run of the
   // logical order (in triangle mode of the tiles that exist, so that every
   // XCD gets the same number).
-  const int lw = logical_wg();
+  int lw, kp = 0;
+  if constexpr (kSplit) {
+    const int jj = blockIdx.x >> 3;
+    kp = jj / ta.tailq;
+    lw = (blockIdx.x & 7) * ta.q + ta.qmain + jj % ta.tailq;
+  } else {
+    lw = ta.q ? (blockIdx.x & 7) * ta.q + (blockIdx.x >> 3) : logical_wg();
+  }
   int bi, bj;
   const bool ok = tri ? lw < gr.nreal && tri_tile_of(lw, gr, &bi, &bj)
                       : tile_of(lw, gr, 0, &bi, &bj);
   if (!ok) {
-    if (e.partial && tid == 0) e.partial[lw] = 0.0;
+    if (!kSplit && e.partial && tid == 0) e.partial[lw] = 0.0;
     return;
   }
 
@@ -116,7 +139,9 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   const int fc = lane & 15;   // m (or n) index of this lane's operand element
   const bool cols_in = (i0 + BM <= n) && (j0 + BM <= n) && ((n & 1) == 0);
 
+  if (kSplit && !(cols_in && n % 64 == 0)) return;  // (the host splits interior tiles only)
   if (cols_in && n % 64 == 0) {
+    const int kbeg = kSplit ? kp * ta.klen : 0;    // first k of this workgroup's range
     // Interior tile: each wave moves RPW k rows of L and R per slab straight
     // into LDS (64 lanes x 16 bytes = one 128-double row), DEPTH slabs ahead
     // of the matrix cores; only the slab about to be read is waited for.
@@ -138,7 +163,7 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
       for (int h = 0; h < RPW; ++h) {
         const int row = RPW * wave_u + h;
         const uint32_t off = (uint32_t)((slot * BKD + row) * LDP) * 8u;
-        const size_t grow = (size_t)(sl * BKD + row) * n;
+        const size_t grow = (size_t)(kbeg + sl * BKD + row) * n;
         const char* gl = reinterpret_cast<const char*>(L + grow + i0);
         const char* gr_ = reinterpret_cast<const char*>(R + grow + j0);
         __builtin_amdgcn_global_load_lds((const void*)(gl + lane_b),
@@ -147,7 +172,7 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
                                          (lds_void*)(uintptr_t)(lds_r + off), 16, 0, 0);
       }
     };
-    const int nk = n / BKD;  // a multiple of FLUSHD
+    const int nk = (kSplit ? ta.klen : n) / BKD;  // a multiple of FLUSHD
     for (int d = 0; d < DEPTH && d < nk; ++d) issue(d);
     // The slab loop is unrolled by the 64-k chain length so that the first
     // k-step of every chain is its own code: there each block's finished
@@ -313,8 +338,21 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
     }
   }
 
-  // Epilogue. Output element r of block (a, b) in this lane (the f64 16x16x4
-  // layout, checked on gfx950): row lane / 16 + 4 r, column lane % 16.
+  // Output element r of block (a, b) in this lane (the f64 16x16x4 layout,
+  // checked on gfx950): row lane / 16 + 4 r, column lane % 16.
+  if constexpr (kSplit) {
+    const int slot = (blockIdx.x & 7) * ta.tailq + (blockIdx.x >> 3) % ta.tailq;
+    double* out = ta.part + ((size_t)slot * ta.kparts + kp) * (BM * BM);
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(wm0 + a * 16 + fr + 4 * r) * BM + wn0 + b * 16 + fc] = sum[a][b][r];
+    return;
+  }
+  // Epilogue.
   double psum = 0.0;
 #pragma unroll
   for (int a = 0; a < FM; ++a)
@@ -327,21 +365,74 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
   if (e.partial) store_partial(e.partial, lw, psum, red);
 }
 
-}  // namespace
+// The split tail's tiles: the kparts range sums added in a fixed order, then
+// the epilogue and the tile's partial sum. One workgroup per tile slot.
+constexpr int NTR = 256;
+__global__ __launch_bounds__(NTR) void tail_reduce_kernel(int n, Grid gr, int tri, Epilogue e,
+                                                          TailArgs ta) {
+  __shared__ double red[NTR / 64];
+  const int slot = blockIdx.x;
+  const int lw = (slot / ta.tailq) * ta.q + ta.qmain + slot % ta.tailq;
+  int bi, bj;
+  if (!(lw < gr.nreal && tri_tile_of(lw, gr, &bi, &bj))) {
+    if (e.partial && threadIdx.x == 0) e.partial[lw] = 0.0;
+    return;
+  }
+  const double* p = ta.part + (size_t)slot * ta.kparts * (BM * BM);
+  double psum = 0.0;
+  for (int idx = threadIdx.x; idx < BM * BM; idx += NTR) {
+    double v = 0.0;
+    for (int k = 0; k < ta.kparts; ++k) v += p[(size_t)k * (BM * BM) + idx];
+    epilogue_element(e, n, tri, bi * BM + idx / BM, bj * BM + idx % BM, v, psum);
+  }
+  if (e.partial) store_partial(e.partial, lw, psum, red);
+}
 
-namespace {
 int launch_wgs(const Grid& gr, int tri) { return tri ? (gr.nreal + 7) / 8 * 8 : gr.nwg; }
+
 }  // namespace
 
 int gemm_partial_slots(int n, int tri) { return launch_wgs(make_grid(n, tri, BM), tri); }
 
+size_t gemm_tail_scratch_elems(int n) {
+  // 8 XCDs x at most 32 CUs' worth of split tiles (tailq kparts <= CUs per XCD)
+  return n >= 2048 && n % BM == 0 ? (size_t)8 * 32 * BM * BM : 0;
+}
+
 hipError_t gemm_f64(const double* L, const double* R, int n, int tri, const Epilogue& e,
-                    hipStream_t stream) {
+                    hipStream_t stream, double* scratch, size_t scratch_elems) {
   if (n <= 0) return hipSuccess;
   if (!L || !R) return hipErrorInvalidValue;  // never launch on a missing operand
   Grid gr = make_grid(n, tri, BM);
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3(launch_wgs(gr, tri)), dim3(NT), 0, stream, L, R, n, gr,
-                     tri, e);
+  if (tri && scratch && n % BM == 0) {
+    static thread_local int ncu = 0;
+    if (!ncu) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 256;
+    }
+    const int cus = ncu / 8 > 0 ? ncu / 8 : 1;   // CUs per XCD
+    const int q = (gr.nreal + 7) / 8;
+    const int tailq = q % cus, qmain = q - tailq;
+    if (tailq > 0 && qmain > 0) {
+      int kp = cus / tailq < 4 ? cus / tailq : 4;
+      while (kp > 1 && (n % (kp * 64) != 0 || (size_t)8 * tailq * kp * BM * BM > scratch_elems))
+        --kp;
+      if (kp > 1) {
+        const TailArgs ta{q, qmain, tailq, kp, n / kp, scratch};
+        hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3(8 * qmain), dim3(NT), 0, stream, L, R, n,
+                           gr, tri, e, ta);
+        hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(8 * tailq * kp), dim3(NT), 0, stream, L, R,
+                           n, gr, tri, e, ta);
+        hipLaunchKernelGGL(tail_reduce_kernel, dim3(8 * tailq), dim3(NTR), 0, stream, n, gr, tri, e,
+                           ta);
+        return hipGetLastError();
+      }
+    }
+  }
+  hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3(launch_wgs(gr, tri)), dim3(NT), 0, stream, L, R,
+                     n, gr, tri, e, TailArgs{});
   return hipGetLastError();
 }
 

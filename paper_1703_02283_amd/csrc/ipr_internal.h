@@ -55,8 +55,13 @@ int gemm_partial_slots(int n, int tri);
 // D = L^T R (n x n, row-major, leading dimension n) in FP64 on the matrix
 // cores, with the epilogue above. L^T R equals L R whenever L is symmetric,
 // which holds for every left operand of the iteration.
+// With `scratch` (scratch_elems >= gemm_tail_scratch_elems(n) doubles,
+// device), a triangle product whose tiles do not fill whole rounds of the CUs
+// splits its last tiles along k among all CUs.
 hipError_t gemm_f64(const double* L, const double* R, int n, int tri,
-                    const Epilogue& e, hipStream_t stream);
+                    const Epilogue& e, hipStream_t stream, double* scratch = nullptr,
+                    size_t scratch_elems = 0);
+size_t gemm_tail_scratch_elems(int n);
 
 // sqrt(sum of slots[0..count)) into *out (device), fixed summation order.
 hipError_t reduce_fro(const double* slots, int count, double* out, hipStream_t stream);

@@ -123,6 +123,8 @@ struct Work {
   double* slP;
   double* slS;
   double* Ar;   // approximate storage: A as stored
+  double* tail; // split tail of the FP64 triangle products
+  size_t tail_elems;
 };
 
 // digits per operand of the int8-slice products (0 when the dtype does not use them)
@@ -158,6 +160,8 @@ size_t carve(int n, int p, int dtype, int slices, bool store, Work* w, void* bas
   w->slP = emul ? c.take<double>(nn) : nullptr;
   w->slS = emul ? c.take<double>(nn) : nullptr;
   w->Ar = store ? c.take<double>(nn) : nullptr;
+  w->tail_elems = gemm_tail_scratch_elems(n);
+  w->tail = w->tail_elems ? c.take<double>(w->tail_elems) : nullptr;
   *ok = c.ok();
   return c.used;
 }
@@ -268,7 +272,7 @@ struct Prod {
                         st);
     } else if (!lowp_dtype) {
       if ((err = start()) != hipSuccess) return err;
-      err = gemm_f64(L, R, n, tri, e, st);
+      err = gemm_f64(L, R, n, tri, e, st, w->tail, w->tail_elems);
     } else {
       const int a = slot_for(L, -1, &err);
       if (err != hipSuccess) return err;
