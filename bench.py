@@ -421,6 +421,9 @@ def main():
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
                      "traffic": traffic_from_profile(n),
                      "launches": g_n, "avg_launch_ms": g_ms / g_n if g_n else None,
+                     "launch_note": "per product; a triangle product whose tiles leave a partial "
+                                    "last round is three kernel launches (whole-round tiles, the "
+                                    "last round's tiles split along k, tail_reduce_kernel)",
                      "flops_per_launch": g_fl / g_n if g_n else None},
     }
 
