@@ -12,6 +12,10 @@
 //  * gemm_lp: D = L^T R from two such operands on the matrix cores with fp32
 //    accumulation, then the float64 epilogue shared with the FP64 kernel
 //    (details at the kernel).
+//  * slices_split / gemm_slices: FP64-accurate products from int8 digit
+//    slices (error-free splitting), the same kernel with int8 operands and
+//    exact int32 accumulation, one launch per level of digit pairs (details
+//    above colmax_kernel).
 #include <algorithm>
 #include <cstdint>
 
