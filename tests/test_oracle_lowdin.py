@@ -39,3 +39,14 @@ def test_back_transformed_vectors_solve_the_generalised_problem():
     c = x @ y
     assert np.allclose(h @ c, s @ c * e, atol=1e-8 * np.abs(e).max())
     assert np.allclose(c.T @ s @ c, np.eye(150), atol=1e-9)
+
+
+def test_overlap_generator_is_the_kernel_matrix_and_h_is_symmetric():
+    s, h = w.overlap_and_hamiltonian(300, seed=9, box=15.0)
+    assert np.array_equal(s, w.kernel_matrix(300, seed=9, box=15.0))
+    assert np.array_equal(h, h.T)
+    # kinetic form: H_ij / S_ij = (3 - d^2 / 2) / 4 off the diagonal, with d^2 = -2 log S_ij
+    i, j = np.triu_indices(300, 1)
+    keep = s[i, j] > 1e-6
+    d2 = -2.0 * np.log(s[i, j][keep])
+    assert np.allclose(h[i, j][keep] / s[i, j][keep], (3.0 - d2 / 2.0) / 4.0, rtol=1e-9, atol=1e-9)
