@@ -94,14 +94,6 @@ def step_map(m, p: int):
     return m * ((p + 1.0 - m) / p) ** p
 
 
-def step_bounds(a: float, b: float, mu: float, p: int):
-    """Bounds on the spectrum of M after a step with scale mu, from bounds
-    [a, b] before it: g rises on (0, 1), peaks at g(1) = 1, falls after."""
-    ga, gb = step_map(mu * a, p), step_map(mu * b, p)
-    nb = 1.0 if mu * a <= 1.0 <= mu * b else max(ga, gb)
-    return min(ga, gb), nb
-
-
 def mu_cap(p: int) -> float:
     """Largest scaled top of the spectrum: 1.98 (< 2, eq. (2)); for p = 1 the
     m with g(m) = m (2 - m) = 1/2, 1 + 1/sqrt(2), so that the step does not
@@ -109,29 +101,32 @@ def mu_cap(p: int) -> float:
     return 1.0 + np.sqrt(0.5) if p == 1 else 1.98
 
 
-def choose_mu(a: float, b: float, p: int) -> float:
-    """Scale factor of a dynamically scaled step (a reading beyond the paper):
-    the mu in [1, mu_cap(p) / b] maximising min(g(mu a), g(mu b)), the lower
-    end after the step; 1 once a >= 1/2. mu b < 2 keeps the step inside
-    eq. (2). Found by bisection on g(mu a) - g(mu b)."""
-    if not (a > 0.0 and b > 0.0) or a >= 0.5:
+def scaled_step_factor(m: np.ndarray, p: int) -> float:
+    """Scale factor mu of one dynamically scaled step (a reading beyond the
+    paper), from the eigenvalues m of M_k: the step maps each eigenvalue m_i to
+    g(mu m_i), and mu is the value in [1, mu_cap(p) / max m] for which the
+    smallest of them after the step is largest; mu = 1 (plain step) once
+    min m >= 1/2, where the iteration is already quadratic.
+
+    Found by brute force: min_i g(mu m_i) on a grid of 100001 values of mu,
+    then on a grid of 2001 values between the best point's neighbours. Since g
+    rises up to its peak at 1 and falls after it, min_i g(mu m_i) is the
+    smaller of the values at the two ends of the spectrum."""
+    m = np.asarray(m, dtype=np.float64)
+    lo, top = float(m.min()), float(m.max())
+    if not (lo > 0.0) or lo >= 0.5:
         return 1.0
-    hi = mu_cap(p) / b
+    hi = mu_cap(p) / top
     if hi <= 1.0:
         return 1.0
-    f = lambda mu: step_map(mu * a, p) - step_map(mu * b, p)
-    if f(hi) <= 0.0:
-        return hi
-    if f(1.0) >= 0.0:
-        return 1.0
-    lo, up = 1.0, hi
-    for _ in range(60):
-        mid = 0.5 * (lo + up)
-        if f(mid) < 0.0:
-            lo = mid
-        else:
-            up = mid
-    return lo
+
+    def lower_end(mu):
+        return np.minimum(step_map(mu * lo, p), step_map(mu * top, p))
+
+    grid = np.linspace(1.0, hi, 100001)
+    j = int(np.argmax(lower_end(grid)))
+    fine = np.linspace(grid[max(j - 1, 0)], grid[min(j + 1, grid.size - 1)], 2001)
+    return float(fine[int(np.argmax(lower_end(fine)))])
 
 
 def start_poly(a: np.ndarray, p: int, b) -> np.ndarray:
@@ -203,7 +198,7 @@ def _make_start(a, p, init, poly):
 
 def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 100,
           evaluation: str = "coupled", poly=(1.0, 0.0, 0.0),
-          floor_window: int = 3, dynamic=None) -> Result:
+          floor_window: int = 3, scaled=None) -> Result:
     """Run the iteration of eq. (1) until ||I - C^p A||_F < tol.
 
     evaluation:
@@ -212,16 +207,13 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
       "literal"        X = C^p A; C <- ((p + 1) C - C X) / p (eq. (1) as printed).
       "newton_schulz"  p = 1 only: C <- C (2I - A C), symmetrised (Section II).
 
-    dynamic=(s, theta): the dynamically scaled coupled iteration from the
-    scaled identity at scale s >= lambda_max(A), with theta an estimate of
-    lambda_min(A): bounds [lo, hi] on the spectrum of M_k start at
-    [min(theta / s, 1), 1]; mu_0 = choose_mu(lo, hi) is folded into the start
-    (C_0 = (s / mu_0)^{-1/p} I); step k uses N = ((p + 1) I - mu_k M)/p,
-    C <- mu_k^{1/p} C N, M <- N^p mu_k M, the bounds follow step_bounds, and
-    mu_{k+1} = choose_mu of the new bounds; whenever rho = ||I - M_k||_F < 1,
-    the bounds are narrowed to [1 - rho, 1 + rho]. dynamic=(s, theta, (j, t)):
-    in addition, before step j (after its convergence test) the lower bound
-    becomes min(t, hi), t an estimate of lambda_min(M_j) (an input, like theta).
+    scaled=s: the dynamically scaled coupled iteration (a reading beyond the
+    paper) from the scaled identity C_0 = s^{-1/p} I, s >= lambda_max(A).
+    Step k uses N = ((p + 1) I - mu_k M)/p, C <- mu_k^{1/p} C N,
+    M <- N^p mu_k M, with mu_k = scaled_step_factor of the eigenvalues of M_k.
+    Those eigenvalues are followed exactly: the spectrum of A (numpy's
+    eigvalsh) divided by s, then mapped by g(mu_k m) at every step (M_k is a
+    polynomial in A, and each step maps its eigenvalues by g).
 
     The returned iteration count is the number of updates applied. Status:
     OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
@@ -236,17 +228,13 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
         raise ValueError("Newton-Schulz order is the p = 1 case")
     n = a.shape[0]
     eye = np.eye(n)
-    c = _make_start(a, p, init, poly)
-    mu = 1.0
-    if dynamic is not None:
+    if scaled is not None:
         if evaluation != "coupled":
             raise ValueError("the scaled iteration is a coupled form")
-        s, theta = dynamic[0], dynamic[1]
-        reest = dynamic[2] if len(dynamic) > 2 else None
-        lo, hi = min(theta / s, 1.0), 1.0
-        mu0 = choose_mu(lo, hi, p)
-        c = (s / mu0) ** (-1.0 / p) * np.eye(n)
-        lo, hi = lo * mu0, mu0
+        c = float(scaled) ** (-1.0 / p) * np.eye(n)
+        m_eig = np.linalg.eigvalsh(a) / float(scaled)
+    else:
+        c = _make_start(a, p, init, poly)
     m = matpow(c, p) @ a if evaluation == "coupled" else None
     rhos = []
     best = np.inf
@@ -264,8 +252,6 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
         rhos.append(rho)
         if not np.isfinite(rho) or rho > 1e6:
             return Result(c, EDIVERGED, k, rhos)
-        if dynamic is not None and rho < 1.0:
-            lo, hi = max(lo, 1.0 - rho), min(hi, 1.0 + rho)
         if rho < tol:
             tau = true_residual(c, a, p)
             if tau < tol:
@@ -280,17 +266,15 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
                     return Result(c, EFLOOR, k, rhos, true_residual(c, a, p))
         if k == max_iter:
             break
-        if evaluation == "coupled" and dynamic is not None:
-            if reest is not None and k == reest[0]:
-                lo = min(reest[1], hi)
+        if evaluation == "coupled" and scaled is not None:
+            mu = scaled_step_factor(m_eig, p)
             nmat = ((p + 1) * eye - mu * m) / p
             c = sym(mu ** (1.0 / p) * (c @ nmat))
             m = mu * m
             for _ in range(p):
                 m = nmat @ m
             m = sym(m)
-            lo, hi = step_bounds(lo, hi, mu, p)
-            mu = choose_mu(lo, hi, p)
+            m_eig = step_map(mu * m_eig, p)
         elif evaluation == "coupled":
             nmat = eye + r / p
             c = sym(c @ nmat)
@@ -327,6 +311,29 @@ def spectral_count(lam: np.ndarray, p: int, c0: np.ndarray, tol: float,
             return max_iter + 1, rhos
         c = scalar_step(c, lam, p)
     return max_iter + 1, rhos
+
+
+def scaled_spectral_count(lam: np.ndarray, p: int, s: float, tol: float,
+                          max_iter: int = 200):
+    """Iteration count and residual trajectory of the dynamically scaled
+    iteration (``solve(scaled=s)``) in exact arithmetic, per eigenvalue: from
+    C_0 = s^{-1/p} I the eigenvalues of M_0 are lam / s, and step k maps them
+    by m <- g(mu_k m) with mu_k = scaled_step_factor(m). The residual is
+    ||I - M_k||_F = sqrt(sum (1 - m)^2). Returns (count, rho_list, mu_list);
+    count = max_iter + 1 when tol is not reached."""
+    m = np.asarray(lam, dtype=np.float64) / float(s)
+    rhos, mus = [], []
+    for k in range(max_iter + 1):
+        rho = float(np.sqrt(np.sum((1.0 - m) ** 2)))
+        rhos.append(rho)
+        if rho < tol:
+            return k, rhos, mus
+        if not np.isfinite(rho) or rho > 1e6:
+            break
+        mu = scaled_step_factor(m, p)
+        mus.append(mu)
+        m = step_map(mu * m, p)
+    return max_iter + 1, rhos, mus
 
 
 def spectral_start(lam: np.ndarray, p: int, init: str, sigma: float,

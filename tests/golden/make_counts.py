@@ -18,11 +18,20 @@ import workloads as w                       # noqa: E402
 from oracle import iteration as it          # noqa: E402
 
 
-def counts(lam, p, sigma, tol):
+def counts(lam, p, sigma, tol, a=None):
+    """Counts from the scaled identity and from eq. (3); with the matrix given,
+    also the power-scale start's scale (the oracle's repeated squaring, at
+    most 6 squarings) and the count of the dynamically scaled iteration from
+    it, both in exact arithmetic on the known spectrum."""
     out = {}
     for init in ("identity", "paper"):
         k, rho = it.spectral_count(lam, p, it.spectral_start(lam, p, init, sigma), tol, 400)
         out[init] = k
+    if a is not None:
+        s, sq = it.power_scale(a, p, 6, scaled_steps=True)
+        k, _, mus = it.scaled_spectral_count(lam, p, s, tol)
+        out["power_scale"] = {"scale": s, "squarings": sq}
+        out["scaled"] = k
     return out
 
 
@@ -37,17 +46,19 @@ def main():
     sig = math.sqrt(it.norm_1(a) * it.norm_inf(a))
     rec["kernel_n4096_seed0"] = {"sigma": sig, "tol": 1e-10, "lam_min": float(lam[0]),
                                  "lam_max": float(lam[-1]),
-                                 **{f"p{p}": counts(lam, p, sig, 1e-10) for p in (1, 2, 3)}}
+                                 **{f"p{p}": counts(lam, p, sig, 1e-10, a) for p in (1, 2, 3)}}
     for kappa in (1e2, 1e4):
         a, lam = w.householder_spd(16384, kappa, seed=0)
         sig = math.sqrt(it.norm_1(a) * it.norm_inf(a))
         rec[f"householder_n16384_kappa{kappa:g}_seed0"] = {
-            "sigma": sig, "tol": 1e-10, "p2": counts(lam, 2, sig, 1e-10)}
+            "sigma": sig, "tol": 1e-10, "p2": counts(lam, 2, sig, 1e-10, a)}
         del a
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "iteration_counts.json")
     with open(path, "w") as f:
         json.dump({"source": "oracle.iteration.spectral_count on workloads generators "
-                             "(eq. (1) per eigenvalue; starts: scaled identity and eq. (3))",
+                             "(eq. (1) per eigenvalue; starts: scaled identity and eq. (3)); "
+                             "scaled: oracle.iteration.scaled_spectral_count from the "
+                             "oracle's power_scale",
                    "counts": rec}, f, indent=1)
     print(json.dumps(rec, indent=1))
 

@@ -50,7 +50,14 @@ def test_householder_16384_p2(ipr, kappa, headline):
     assert res.residual_true < 1e-10
     assert err <= 1e-10
     if headline:
+        # the oracle's power scale and its exact-arithmetic count of the
+        # scaled iteration on the known spectrum (golden file)
+        gs = GOLD[f"householder_n16384_kappa{kappa:g}_seed0"]["p2"]
+        say("  scale", res.init_scale, "golden", gs["power_scale"]["scale"],
+            "iterations golden", gs["scaled"])
         assert res.iters_fp64 < g       # fewer iterations than the plain iteration
+        assert abs(res.iters_fp64 - gs["scaled"]) <= 1
+        assert abs(res.init_scale - gs["power_scale"]["scale"]) <= 1e-9 * res.init_scale
         assert lam.max() <= res.init_scale < math.sqrt(res.norm1 * res.norminf)
         assert lam.min() * (1 - 1e-12) <= res.lmin_est <= lam.max()
     else:
@@ -78,6 +85,17 @@ def test_kernel_matrix_4096(ipr, kernel4096, p):
     assert res.status == ipr.IPR_OK, res.as_dict()
     assert err <= 1e-10
     assert abs(res.iters_fp64 - g) <= 1
+    # power-scale start and scaled steps: the oracle's scale and its
+    # exact-arithmetic count of the scaled iteration (golden file)
+    gs = GOLD["kernel_n4096_seed0"][f"p{p}"]
+    C, res = ipr.ipr_solve(dev(a), p, 1e-10, schedule=ipr.ipr_schedule_default(
+        scale_squarings=6, dynamic_scaling=1))
+    err = it.rel_fro(host(C), ref)
+    say("  scaled: status", res.status, "iters", res.iters_fp64, "golden", gs["scaled"], "err", err)
+    assert res.status == ipr.IPR_OK, res.as_dict()
+    assert err <= 1e-10
+    assert abs(res.init_scale - gs["power_scale"]["scale"]) <= 1e-9 * res.init_scale
+    assert -1 <= res.iters_fp64 - gs["scaled"] <= 2
 
 
 def test_householder_16384_p2_int8_slice_products(ipr):

@@ -145,59 +145,79 @@ def test_power_scale_bounds_lambda_max_and_tightens():
         prev = s
 
 
-def test_scale_factor_rule_maximises_the_lower_end():
+def test_scale_factor_closed_forms():
+    # Where the cap does not bind, the best mu balances the two ends of the
+    # spectrum, g(mu a) = g(mu b). For p = 1, g(m) = m (2 - m) is symmetric about
+    # 1, so mu (a + b) = 2. For p = 2, g(m) = m (3 - m)^2 / 4 and the balance
+    # a (3 - mu a)^2 = b (3 - mu b)^2 divided by (a - b) is the quadratic
+    # mu^2 (a^2 + ab + b^2) - 6 mu (a + b) + 9 = 0, whose smaller root is
+    # mu = 3 (a + b - sqrt(ab)) / (a^2 + ab + b^2).
     from oracle import iteration as it
+    for a, b in ((0.3, 1.0), (0.2, 0.9), (0.45, 0.8)):
+        assert abs(it.scaled_step_factor(np.array([a, 0.5 * (a + b), b]), 1)
+                   - 2.0 / (a + b)) < 1e-7
+        mu2 = 3.0 * (a + b - np.sqrt(a * b)) / (a * a + a * b + b * b)
+        assert mu2 * b < it.mu_cap(2)
+        assert abs(it.scaled_step_factor(np.array([a, b]), 2) - mu2) < 1e-7
+    # a spectrum reaching far down: the lower end still rises at the cap
     for p in (1, 2, 3, 4):
-        for a, b in ((1e-4, 1.0), (0.01, 0.7), (0.2, 1.0), (0.3, 0.9)):
-            mu = it.choose_mu(a, b, p)
-            assert 1.0 <= mu and mu * b < 2.0
-            grid = np.linspace(1.0, it.mu_cap(p) / b, 20001)
-            best = np.max(np.minimum(it.step_map(grid * a, p), it.step_map(grid * b, p)))
-            got = min(it.step_map(mu * a, p), it.step_map(mu * b, p))
-            assert got >= best * (1 - 1e-6)
-            assert it.choose_mu(0.6, 1.0, p) == 1.0          # quadratic phase: unscaled
-        # step_bounds encloses g over the scaled interval (dense sampling)
-        for a, b, mu in ((1e-3, 1.0, 1.9), (0.4, 0.8, 1.5), (0.9, 1.0, 1.0)):
-            lo, hi = it.step_bounds(a, b, mu, p)
-            x = np.linspace(mu * a, mu * b, 10001)
-            g = it.step_map(x, p)
-            assert lo <= g.min() + 1e-15 and g.max() <= hi + 1e-15
-            assert abs(lo - g.min()) < 1e-12 and hi - g.max() < 1e-6
+        assert abs(it.scaled_step_factor(np.array([1e-4, 0.5]), p)
+                   - it.mu_cap(p) / 0.5) < 1e-12
+        # quadratic phase, and a spectrum whose top is already at the cap
+        assert it.scaled_step_factor(np.array([0.6, 1.0]), p) == 1.0
+        assert it.scaled_step_factor(np.array([0.01, it.mu_cap(p)]), p) == 1.0
+
+
+def test_scale_factor_beats_every_other_scale_on_whole_spectra():
+    # brute force over every eigenvalue (not only the ends): no scale in the
+    # allowed range gives a larger smallest eigenvalue after the step
+    from oracle import iteration as it
+    rng = np.random.default_rng(5)
+    for p in (1, 2, 3, 4):
+        for _ in range(4):
+            m = np.exp(rng.uniform(np.log(1e-5), 0.0, 200)) * rng.uniform(0.3, 1.0)
+            mu = it.scaled_step_factor(m, p)
+            assert 1.0 <= mu and mu * m.max() <= it.mu_cap(p) * (1 + 1e-15)
+            got = np.min(it.step_map(mu * m, p))
+            for t in np.linspace(1.0, it.mu_cap(p) / m.max(), 3001):
+                assert np.min(it.step_map(t * m, p)) <= got * (1 + 1e-9)
 
 
 def test_scaled_iteration_reaches_the_root_in_fewer_steps():
+    # the dense scaled iteration: the exact-arithmetic count of the same
+    # schedule (per eigenvalue), the root by definition, fewer iterations than
+    # the plain iteration from the same start
     import workloads as w
     from oracle import iteration as it
     for p in (1, 2, 3):
         a, lam, _ = w.spd_log_spectrum(120, 1e4, seed=60 + p)
-        s, _ = it.power_scale(a, p, 6)
-        plain = it.solve(a, p, 1e-10, init=s ** (-1.0 / p) * np.eye(120))
-        for theta in (lam.min(), 3.0 * lam.min()):      # exact and overestimated lambda_min
-            r = it.solve(a, p, 1e-10, dynamic=(s, theta))
-            assert r.status == it.OK and r.iters < plain.iters
+        for s in (np.sqrt(it.norm_1(a) * it.norm_inf(a)), it.power_scale(a, p, 6, True)[0]):
+            plain = it.solve(a, p, 1e-10, init=s ** (-1.0 / p) * np.eye(120))
+            r = it.solve(a, p, 1e-10, scaled=s)
+            k, rho, mus = it.scaled_spectral_count(lam, p, s, 1e-10)
+            assert r.status == it.OK and r.iters < plain.iters and r.iters == k
+            assert all(mu >= 1.0 for mu in mus) and mus[0] > 1.0
             assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
+            # the residual trajectory follows the exact one until the rounding floor
+            for x, y in zip(r.rho, rho):
+                if y > 1e-6:
+                    assert abs(x - y) <= 1e-8 * y
 
 
-def test_reestimated_lower_end_recovers_the_exact_count():
-    # theta 7x too large (what a short Lanczos run on A gives for a dense low
-    # spectrum) costs iterations; replacing the lower bound before step j by
-    # the exact lambda_min(M_j) brings the count back to that of the exact
-    # theta, for any early j, and the iteration still reaches the root
-    import workloads as w
+def test_scaled_iteration_on_diagonal_matrices_is_the_scalar_recursion():
+    # diagonal A: every product is exact up to one rounding per entry, and the
+    # scaled iteration's diagonal follows c <- mu^{1/p} c (p + 1 - mu c^p lam)/p
     from oracle import iteration as it
-    for p in (1, 2, 3):
-        a, lam, _ = w.spd_log_spectrum(160, 1e4, seed=70 + p)
-        s, _ = it.power_scale(a, p, 6, scaled_steps=True)
-        th = 7.0 * lam.min()
-        base = it.solve(a, p, 1e-10, dynamic=(s, th))
-        exact = it.solve(a, p, 1e-10, dynamic=(s, lam.min()))
-        assert exact.iters < base.iters
-        for j in (1, 3):
-            cj = it.solve(a, p, 1e-30, max_iter=j, dynamic=(s, th)).c
-            t = np.linalg.eigvalsh(it.matpow(cj, p) @ a).min()
-            r = it.solve(a, p, 1e-10, dynamic=(s, th, (j, t)))
-            assert r.status == it.OK and r.iters == exact.iters
-            assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
+    lam = np.array([1e-3, 0.02, 0.3, 0.7, 1.0])
+    p, s = 2, 1.0
+    r = it.solve(np.diag(lam), p, 1e-12, scaled=s)
+    k, _, mus = it.scaled_spectral_count(lam, p, s, 1e-12)
+    assert r.status == it.OK and r.iters == k
+    c = np.full_like(lam, s ** (-1.0 / p))
+    for mu in mus[:k]:
+        c = mu ** (1.0 / p) * c * (p + 1 - mu * c ** p * lam) / p
+    assert np.allclose(np.diag(r.c), c, rtol=1e-14, atol=0)
+    assert np.allclose(np.diag(r.c), lam ** (-1.0 / p), rtol=1e-12, atol=0)
 
 
 def test_scaled_iteration_keeps_the_p1_floor():
@@ -209,6 +229,6 @@ def test_scaled_iteration_keeps_the_p1_floor():
     a, lam, _ = w.spd_log_spectrum(200, 6e4, seed=10)
     s, _ = it.power_scale(a, 1, 6)
     plain = it.solve(a, 1, 1e-10, init=s ** (-1.0) * np.eye(200))
-    r = it.solve(a, 1, 1e-10, dynamic=(s, 1.5 * lam.min()))
+    r = it.solve(a, 1, 1e-10, scaled=s)
     assert plain.status == it.OK and r.status == it.OK and r.iters < plain.iters
     assert r.residual_true < 2.0 * plain.residual_true
