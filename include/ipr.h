@@ -42,7 +42,9 @@ typedef enum {
   IPR_EARG = 1,        /* invalid argument or workspace too small */
   IPR_EMAXITER = 2,    /* max_iter updates applied without reaching tol */
   IPR_EFLOOR = 3,      /* the residual stopped falling above tol (precision floor) */
-  IPR_EDIVERGED = 4,   /* NaN/Inf or residual > 1e6 */
+  IPR_EDIVERGED = 4,   /* NaN/Inf or residual > 1e6, again after one restart from the
+                          scaled identity (ipr_solve; not for the LITERAL order or
+                          approximate storage, which report the first divergence) */
   IPR_EHIP = 5,        /* a HIP runtime call failed */
   IPR_EGUARD = 6       /* a requested start violates eq. (2) and fallback was disabled */
 } ipr_status;
@@ -74,7 +76,9 @@ typedef enum {
 /* Order in which the products of eq. (1) are evaluated (Section II). */
 typedef enum {
   IPR_EVAL_COUPLED = 0,       /* M_k = C_k^p A carried along: N_k = ((p+1) I - M_k)/p,
-                                 C_{k+1} = C_k N_k, M_{k+1} = N_k^p M_k (p + 1 products; default) */
+                                 C_{k+1} = C_k N_k, M_{k+1} = N_k^p M_k (p + 1 products; default;
+                                 for p a power of two >= 4, N_k^p by repeated squaring:
+                                 log2(p) + 2 products, 4 for p = 4) */
   IPR_EVAL_LITERAL = 1,       /* eq. (1) as printed: X = C_k^p A, C_{k+1} = ((p+1) C_k - C_k X)/p,
                                  full products, no symmetrisation (p + 1 products; a diagnostic:
                                  rounding errors grow beyond small condition numbers) */
@@ -126,6 +130,26 @@ typedef struct {
                           iteration from the scaled identity (IPR_EARG otherwise); a coarse
                           format ends on its floor (IPR_EFLOOR) */
   int store_bits;      /* stored mantissa bits (FLOAT) or fractional bits (FIXED) */
+  int store_regime;    /* with store_format: 0 = storage only (default: the stored matrices are
+                          rounded, arithmetic in FP64); 1 = all arithmetic (Section IV, "all
+                          involved calculations"): every scalar operation is one float64
+                          operation rounded to the type. Then A~ = rnd(A), c = rnd(sigma^(-1/p)),
+                          c_p = rnd(c^p), C_0 = c I, M_0 = rnd(c_p A~), N = rnd(I + rnd(rnd(I - M)/p)),
+                          and each product sums acc <- rnd(acc + rnd(l_ki r_kj)) over k in
+                          increasing order (upper triangle, mirrored) on the vector units */
+  const double* hist_ref; /* device n x n or NULL: ipr_solve writes ||C_k - hist_ref||_F to
+                          hist_err[k] for every iterate k it forms (e.g. the float64 root, for
+                          the error curves of Section IV-C): the coupled FP64 iteration and
+                          both approximate regimes (not the low-precision bulk phase) */
+  double* hist_err;    /* host, hist_len doubles (or NULL) */
+  double* hist_rho;    /* host, hist_len doubles (or NULL): ||I - M_k||_F per iterate (NaN for
+                          an iterate whose M was not formed) */
+  int hist_len;        /* capacity of hist_err / hist_rho; entries k >= hist_len are dropped */
+  int bulk_force;      /* 1: run a BF16/FP16/FP8 bulk phase also for p >= 2 (default 0: skipped
+                          there and reported in ipr_result.bulk_skipped). For p >= 2 the phase
+                          leaves an error that does not commute with A; the coupled FP64 steps
+                          do not remove it, so the solve restarts in FP64 (fallback_used) and
+                          the phase was spent for nothing */
 } ipr_schedule;
 
 typedef struct {
@@ -133,7 +157,8 @@ typedef struct {
   int iters_bulk;      /* updates applied in the low-precision bulk phase */
   int iters_fp64;      /* updates applied in FP64 */
   int fallback_used;   /* 1 if IDENTITY was used instead: the requested start failed the
-                          guard, or the low-precision phase failed and FP64 restarted */
+                          guard, the low-precision phase failed and FP64 restarted, or the
+                          iteration diverged and restarted once */
   int gemms;           /* matrix products launched (all phases) */
   double residual_proxy; /* last tracked ||I - C^p A||_F */
   double residual_true;  /* ||I - C^p A||_F computed from C and A (NaN if not verified) */
@@ -155,6 +180,9 @@ typedef struct {
   int reest_iter;        /* dynamic_scaling: the step before which lambda_min(M_k) was estimated
                             again (once its bound reached 0.03; 0 if not) */
   double lmin_reest;     /* that estimate (0 if none) */
+  int bulk_skipped;      /* 1: a BF16/FP16/FP8 bulk dtype was requested but not run (p >= 2
+                            without schedule.bulk_force; in ipr_solve_batched every p >= 2
+                            item): the solve ran in FP64 */
 } ipr_result;
 
 #define IPR_MLP_NIN 16
@@ -224,8 +252,10 @@ int ipr_gemm(const double* dL, const double* dR, const double* dX, double* dD, i
 /* Low-precision product (the storage-approximation regime of Sections III-B
  * and IV): L and R are rounded to `dtype` with per-128x128-tile power-of-two
  * scales (fp16, fp8) or none (bf16), multiplied on the matrix cores with fp32
- * accumulation; D (float64) = L^T R. dWork >= ipr_gemm_lowp_workspace(n). */
-int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype,
+ * accumulation; D (float64) = L^T R. triangle = 1: only the tiles on and above
+ * the diagonal are computed and D is mirrored from them (for a symmetric
+ * product, as in the iteration). dWork >= ipr_gemm_lowp_workspace(n). */
+int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype, int triangle,
                   void* dWork, size_t work_bytes, hipStream_t stream);
 size_t ipr_gemm_lowp_workspace(int n);
 
@@ -242,12 +272,13 @@ size_t ipr_gemm_lowp_workspace(int n);
  * its column's largest keeps fewer bits than float64 gives it: with 9 slices
  * the n = 8192 and 16384 iterations (kappa = 1e4) stop near 1e-10 instead of
  * 3e-11; 10 slices reach the float64 result. Costs slices (slices + 1) / 2
- * int8 products. Ownership and stream as ipr_gemm; dD must not alias an operand.
+ * int8 products. triangle as in ipr_gemm_lowp. Ownership and stream as ipr_gemm;
+ * dD must not alias an operand.
  * dWork >= ipr_gemm_emul_workspace(n, slices) bytes (device). Errors:
  * IPR_EARG for a null pointer, n < 1, slices outside 1..12, n above 132864
  * (one digit product must fit an int32 accumulation) or a short workspace.
  * A column holding Inf or NaN gives NaN in the matching row or column of D. */
-int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int slices,
+int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int slices, int triangle,
                   void* dWork, size_t work_bytes, hipStream_t stream);
 size_t ipr_gemm_emul_workspace(int n, int slices);
 
@@ -275,7 +306,8 @@ int ipr_norms(const double* dA, int n, double* out, void* dWork, size_t work_byt
  * dFeat (device, batch x 16 float32); offsets/n/p are host arrays, staged
  * into dWork (>= 16 * batch + 1024 bytes). With s = sqrt(||A||_1 ||A||_inf),
  * B = A/s, d = diag B, r_i = sum_j |B_ij|, o_i = r_i - |d_i|, t1 = trace B / n,
- * t2 = ||B||_F^2 / n: log2(n)/10, p/4, t1, t2, log10 t1, log10 t2, t1^2/t2,
+ * t2 = ||B||_F^2 / n: clamp(log2 n, 6, 10)/10 (the training sizes 64..1024),
+ * p/4, t1, t2, log10 t1, log10 t2, t1^2/t2,
  * min d, max d, log10 max(min d, 1e-30), min(d_i - o_i), mean r, sum o / sum|d|,
  * max off-diagonal |B_ij|, std(d)/mean(d), log10 s. All O(n^2). */
 int ipr_features(const double* dA_packed, const int64_t* offsets, const int* n, const int* p,

@@ -28,6 +28,14 @@ Parity pins (tests marked "not gpu" check each of these):
                          (brute force on tiny inputs) and its error bound.
   * approximate storage - against the scalar recursion on diagonal A, the
                          stored-bit floors and the behaviour Section IV-C reports.
+  * all arithmetic     - the rounded product against brute-force scalar loops
+                         with a separately written rounding rule, the rounded
+                         scalar recursion on diagonal A (bit for bit), 52 bits
+                         against the float64 iteration, floors above the
+                         storage-only regime's (Section IV-C).
+  * scaled steps       - the factor against its closed forms (p = 1, 2) and
+                         brute force over whole spectra; the dense count
+                         against the per-eigenvalue count.
   * Loewdin transform  - against scipy's generalised eigenvalues and closed
                          forms.
 Parity unpinned: none of the functions above lacks a pin. The accuracy the

@@ -7,7 +7,8 @@ All features are O(n^2) functions of A (n x n, symmetric) and p. With
 sigma = sqrt(||A||_1 ||A||_inf) (the scale of the start in eq. (3)) and
 B = A / sigma, d = diag(B), s_i = sum_j |B_ij|, o_i = s_i - |d_i|:
 
-  0 log2(n)/10         1 p/4               2 t1 = trace(B)/n
+  0 clamp(log2 n, 6, 10)/10 (the order, clipped to the training sizes)
+  1 p/4                2 t1 = trace(B)/n
   3 t2 = ||B||_F^2/n   4 log10 t1          5 log10 t2
   6 t1^2/t2            7 min d             8 max d
   9 log10 max(min d, 1e-30)               10 min_i (d_i - o_i)  (Gershgorin low)
@@ -34,7 +35,7 @@ def features(a: np.ndarray, p: int) -> np.ndarray:
     t2 = float(np.sum(b * b)) / n
     off = np.abs(b - np.diag(d))
     return np.array([
-        np.log2(n) / 10.0,
+        min(max(np.log2(n), 6.0), 10.0) / 10.0,
         p / 4.0,
         t1,
         t2,

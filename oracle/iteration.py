@@ -208,12 +208,13 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
       "newton_schulz"  p = 1 only: C <- C (2I - A C), symmetrised (Section II).
 
     scaled=s: the dynamically scaled coupled iteration (a reading beyond the
-    paper) from the scaled identity C_0 = s^{-1/p} I, s >= lambda_max(A).
-    Step k uses N = ((p + 1) I - mu_k M)/p, C <- mu_k^{1/p} C N,
-    M <- N^p mu_k M, with mu_k = scaled_step_factor of the eigenvalues of M_k.
-    Those eigenvalues are followed exactly: the spectrum of A (numpy's
-    eigvalsh) divided by s, then mapped by g(mu_k m) at every step (M_k is a
-    polynomial in A, and each step maps its eigenvalues by g).
+    paper) from C_0 = s^{-1/p} q(A/s), s >= lambda_max(A), with
+    q(x) = b0 + b1 x + b2 x^2 given by ``poly`` when init="poly" and q = 1
+    (the scaled identity) otherwise. Step k uses N = ((p + 1) I - mu_k M)/p,
+    C <- mu_k^{1/p} C N, M <- N^p mu_k M, with mu_k = scaled_step_factor of
+    the eigenvalues of M_k. Those eigenvalues are followed exactly: M_0 has
+    q(x)^p x at x = lambda / s (lambda from numpy's eigvalsh of A), and each
+    step maps them by g(mu_k m) (M_k is a polynomial in A).
 
     The returned iteration count is the number of updates applied. Status:
     OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
@@ -231,8 +232,12 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
     if scaled is not None:
         if evaluation != "coupled":
             raise ValueError("the scaled iteration is a coupled form")
-        c = float(scaled) ** (-1.0 / p) * np.eye(n)
-        m_eig = np.linalg.eigvalsh(a) / float(scaled)
+        s = float(scaled)
+        b = poly if init == "poly" else (1.0, 0.0, 0.0)
+        ah = a / s
+        c = s ** (-1.0 / p) * sym(b[0] * np.eye(n) + b[1] * ah + b[2] * (ah @ ah))
+        x = np.linalg.eigvalsh(a) / s
+        m_eig = (b[0] + b[1] * x + b[2] * x * x) ** p * x
     else:
         c = _make_start(a, p, init, poly)
     m = matpow(c, p) @ a if evaluation == "coupled" else None
@@ -314,14 +319,16 @@ def spectral_count(lam: np.ndarray, p: int, c0: np.ndarray, tol: float,
 
 
 def scaled_spectral_count(lam: np.ndarray, p: int, s: float, tol: float,
-                          max_iter: int = 200):
+                          max_iter: int = 200, poly=(1.0, 0.0, 0.0)):
     """Iteration count and residual trajectory of the dynamically scaled
     iteration (``solve(scaled=s)``) in exact arithmetic, per eigenvalue: from
-    C_0 = s^{-1/p} I the eigenvalues of M_0 are lam / s, and step k maps them
-    by m <- g(mu_k m) with mu_k = scaled_step_factor(m). The residual is
-    ||I - M_k||_F = sqrt(sum (1 - m)^2). Returns (count, rho_list, mu_list);
-    count = max_iter + 1 when tol is not reached."""
-    m = np.asarray(lam, dtype=np.float64) / float(s)
+    C_0 = s^{-1/p} q(A/s) the eigenvalues of M_0 are q(x)^p x at x = lam / s
+    (q = 1: lam / s), and step k maps them by m <- g(mu_k m) with
+    mu_k = scaled_step_factor(m). The residual is ||I - M_k||_F =
+    sqrt(sum (1 - m)^2). Returns (count, rho_list, mu_list); count =
+    max_iter + 1 when tol is not reached."""
+    x = np.asarray(lam, dtype=np.float64) / float(s)
+    m = (poly[0] + poly[1] * x + poly[2] * x * x) ** p * x
     rhos, mus = [], []
     for k in range(max_iter + 1):
         rho = float(np.sqrt(np.sum((1.0 - m) ** 2)))

@@ -29,7 +29,9 @@ class IprSchedule(ct.Structure):
                 ("tile", ct.c_int), ("scale_squarings", ct.c_int),
                 ("dynamic_scaling", ct.c_int), ("evaluation", ct.c_int),
                 ("emul_slices", ct.c_int), ("store_format", ct.c_int),
-                ("store_bits", ct.c_int)]
+                ("store_bits", ct.c_int), ("store_regime", ct.c_int),
+                ("hist_ref", ct.c_void_p), ("hist_err", ct.c_void_p), ("hist_rho", ct.c_void_p),
+                ("hist_len", ct.c_int), ("bulk_force", ct.c_int)]
 
 
 class IprResult(ct.Structure):
@@ -44,7 +46,7 @@ class IprResult(ct.Structure):
                 ("gemm_flops", ct.c_double), ("lp_gemm_launches", ct.c_int),
                 ("ms_lp_gemm", ct.c_double), ("lp_gemm_flops", ct.c_double),
                 ("lmin_est", ct.c_double), ("reest_iter", ct.c_int),
-                ("lmin_reest", ct.c_double)]
+                ("lmin_reest", ct.c_double), ("bulk_skipped", ct.c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,9 +80,9 @@ _SIGS = {
     "ipr_gemm": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
                             ct.c_double, ct.c_double, ct.c_double, ct.c_int, ct.c_void_p]),
     "ipr_gemm_lowp": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
-                                 ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+                                 ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ipr_gemm_lowp_workspace": (ct.c_size_t, [ct.c_int]),
-    "ipr_gemm_emul": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int,
+    "ipr_gemm_emul": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_int,
                                  ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ipr_gemm_emul_workspace": (ct.c_size_t, [ct.c_int, ct.c_int]),
     "ipr_lowdin": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int,
@@ -297,15 +299,16 @@ def ipr_gemm_lowp_workspace(n) -> int:
     return int(_fn("ipr_gemm_lowp_workspace")(n))
 
 
-def ipr_gemm_lowp(L, R, dtype, out=None, workspace=None, stream=None):
-    """D = L^T R with operands stored in a low-precision format (fp32 accumulate)."""
+def ipr_gemm_lowp(L, R, dtype, out=None, workspace=None, stream=None, triangle=False):
+    """D = L^T R with operands stored in a low-precision format (fp32 accumulate);
+    triangle: upper tiles computed, D mirrored from them."""
     n = L.shape[0]
     for t, nm in ((L, "L"), (R, "R")):
         _need(t, torch.float64, (n, n), nm)
     D = out if out is not None else torch.empty_like(L)
     ws = workspace if workspace is not None else _workspace(ipr_gemm_lowp_workspace(n), L.device)
-    _check(_fn("ipr_gemm_lowp")(_ptr(L), _ptr(R), _ptr(D), n, int(dtype), _ptr(ws), ws.numel(),
-                                _stream(stream)))
+    _check(_fn("ipr_gemm_lowp")(_ptr(L), _ptr(R), _ptr(D), n, int(dtype), 1 if triangle else 0,
+                                _ptr(ws), ws.numel(), _stream(stream)))
     return D
 
 
@@ -313,16 +316,17 @@ def ipr_gemm_emul_workspace(n, slices=10) -> int:
     return int(_fn("ipr_gemm_emul_workspace")(n, slices))
 
 
-def ipr_gemm_emul(L, R, slices=10, out=None, workspace=None, stream=None):
-    """D = L^T R, FP64-accurate, from int8 digit slices on the matrix cores."""
+def ipr_gemm_emul(L, R, slices=10, out=None, workspace=None, stream=None, triangle=False):
+    """D = L^T R, FP64-accurate, from int8 digit slices on the matrix cores
+    (triangle: upper tiles computed, D mirrored from them)."""
     n = L.shape[0]
     for t, nm in ((L, "L"), (R, "R")):
         _need(t, torch.float64, (n, n), nm)
     D = out if out is not None else torch.empty_like(L)
     ws = workspace if workspace is not None else _workspace(
         ipr_gemm_emul_workspace(n, slices), L.device)
-    _check(_fn("ipr_gemm_emul")(_ptr(L), _ptr(R), _ptr(D), n, int(slices), _ptr(ws), ws.numel(),
-                                _stream(stream)))
+    _check(_fn("ipr_gemm_emul")(_ptr(L), _ptr(R), _ptr(D), n, int(slices), 1 if triangle else 0,
+                                _ptr(ws), ws.numel(), _stream(stream)))
     return D
 
 

@@ -262,6 +262,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
       r.reest_iter = res[i].reest_iter;
       r.lmin_reest = res[i].lmin_reest;
       r.poly_used[0] = 1.0;
+      // the bf16 bulk phase runs for p = 1 items only
+      r.bulk_skipped = (s.bulk_dtype != IPR_FP64 && p[i] >= 2) ? 1 : 0;
     }
     if (res[i].status != IPR_OK && status == IPR_OK) status = res[i].status;
   }

@@ -55,8 +55,8 @@ size_t ipr_gemm_lowp_workspace(int n) {
   return lp_work(n, LP_FP16, &w, nullptr, (size_t)-1, &ok) + 256;
 }
 
-int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype, void* dWork,
-                  size_t work_bytes, hipStream_t stream) {
+int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dtype, int triangle,
+                  void* dWork, size_t work_bytes, hipStream_t stream) {
   g_last_error.clear();
   if (!dL || !dR || !dD || !dWork || n < 1) return fail(IPR_EARG, "ipr_gemm_lowp: bad argument");
   if (dtype != IPR_BF16 && dtype != IPR_FP16 && dtype != IPR_FP8_E4M3)
@@ -70,7 +70,7 @@ int ipr_gemm_lowp(const double* dL, const double* dR, double* dD, int n, int dty
   HIP_TRY(quantize_t(dR, n, dtype, w.rq, w.er, stream));
   Epilogue e;
   e.D = dD;
-  HIP_TRY(gemm_lp(w.lq, w.el, w.rq, w.er, n, dtype, 0, e, stream));
+  HIP_TRY(gemm_lp(w.lq, w.el, w.rq, w.er, n, dtype, triangle ? 1 : 0, e, stream));
   return IPR_OK;
 }
 
@@ -81,8 +81,8 @@ size_t ipr_gemm_emul_workspace(int n, int slices) {
   return emul_work(n, slices, &w, nullptr, (size_t)-1, &ok) + 256;
 }
 
-int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int slices, void* dWork,
-                  size_t work_bytes, hipStream_t stream) {
+int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int slices, int triangle,
+                  void* dWork, size_t work_bytes, hipStream_t stream) {
   g_last_error.clear();
   if (!dL || !dR || !dD || !dWork || n < 1) return fail(IPR_EARG, "ipr_gemm_emul: bad argument");
   if (slices < 1 || slices > kMaxSlices)
@@ -99,7 +99,7 @@ int ipr_gemm_emul(const double* dL, const double* dR, double* dD, int n, int sli
   HIP_TRY(slices_split(dR, n, slices, w.rq, w.er, w.cm, stream));
   Epilogue e;
   e.D = dD;
-  HIP_TRY(gemm_slices(w.lq, w.el, w.rq, w.er, n, slices, w.P, w.S, 0, e, stream));
+  HIP_TRY(gemm_slices(w.lq, w.el, w.rq, w.er, n, slices, w.P, w.S, triangle ? 1 : 0, e, stream));
   return IPR_OK;
 }
 

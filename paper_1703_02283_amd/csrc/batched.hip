@@ -576,6 +576,14 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     }
 
     // ---- FP64 iterations
+    // products per step: C N and N^p (M); for p a power of two >= 4 N^p comes
+    // from log2(p) - 1 squarings and two products, C^p of the final check
+    // from log2(p) squarings
+    const bool binary = p >= 4 && (p & (p - 1)) == 0;
+    int lg = 0;
+    while ((1 << lg) < p) ++lg;
+    const int step_prods = binary ? lg + 2 : p + 1;
+    const int check_prods = binary ? lg + 1 : p;
     double best = 1e300, last_tau = 1e300;
     int stale = 0, failed = 0, k = 0;
     bool reestimated = false;
@@ -596,29 +604,56 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
           res.status = 0;
           break;
         }
-        // ||I - C^p A||_F from p full products
+        // ||I - C^p A||_F from p full products (for p a power of two >= 4:
+        // C^p by repeated squaring, then C^p A)
         __syncthreads();
         if (tid == 0) {
-          const double* src = b.A;
-          for (int j = 1; j <= p; ++j) {
+          if (binary) {
+            const double* P = b.C[ci];
+            int xb = 0;
+            for (int j = 0; j < lg; ++j) {
+              ProdDesc d;
+              d.L = P;
+              d.R = P;
+              d.tri = 1;
+              d.lowp = 0;
+              d.e = WEpi();
+              d.e.D = b.X[xb];
+              P = d.e.D;
+              xb ^= 1;
+              q[j] = d;
+            }
             ProdDesc d;
-            d.L = b.C[ci];
-            d.R = src;
+            d.L = P;
+            d.R = b.A;
             d.tri = 0;
             d.lowp = 0;
             d.e = WEpi();
-            if (j == p) {
-              d.e.alpha = -1.0;
-              d.e.gamma = 1.0;
-            } else {
-              d.e.D = b.X[(j - 1) & 1];
-              src = d.e.D;
+            d.e.alpha = -1.0;
+            d.e.gamma = 1.0;
+            q[lg] = d;
+          } else {
+            const double* src = b.A;
+            for (int j = 1; j <= p; ++j) {
+              ProdDesc d;
+              d.L = b.C[ci];
+              d.R = src;
+              d.tri = 0;
+              d.lowp = 0;
+              d.e = WEpi();
+              if (j == p) {
+                d.e.alpha = -1.0;
+                d.e.gamma = 1.0;
+              } else {
+                d.e.D = b.X[(j - 1) & 1];
+                src = d.e.D;
+              }
+              q[j - 1] = d;
             }
-            q[j - 1] = d;
           }
         }
         __syncthreads();
-        const double tau = sqrt(run_products(q, p, n, tile, &sm));
+        const double tau = sqrt(run_products(q, check_prods, n, tile, &sm));
         res.residual_true = tau;
         if (tau < args.tol) {
           res.status = 0;
@@ -676,30 +711,69 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
         d.e.alpha = mu_k == 1.0 ? 1.0 : pow(mu_k, inv_p);
         d.e.D = b.C[ci ^ 1];
         q[0] = d;
-        const double* src = b.M[mi];
-        for (int j = 1; j <= p; ++j) {
+        auto last = [&](ProdDesc& m) {  // M' and N' = ((p+1)/mu' - M') mu'/p
+          m.e.D = b.M[mi ^ 1];
+          m.e.Nout = b.N[ni ^ 1];
+          m.e.np1 = (p + 1.0) / mu_n;
+          m.e.inv_p = mu_n * inv_p;
+          m.e.pd = 1.0;
+        };
+        int nq = 1;
+        if (binary) {
+          // N^p by repeated squaring: P = N^(p/2), then P (P mu M)
+          const double* P = b.N[ni];
+          int xb = 0;
+          for (int qq = 1; 2 * qq <= p / 2; qq *= 2) {
+            ProdDesc m;
+            m.L = P;
+            m.R = P;
+            m.tri = 1;
+            m.lowp = 0;
+            m.e = WEpi();
+            m.e.D = b.X[xb];
+            P = m.e.D;
+            xb ^= 1;
+            q[nq++] = m;
+          }
           ProdDesc m;
-          m.L = b.N[ni];
-          m.R = src;
+          m.L = P;
+          m.R = b.M[mi];
           m.tri = 1;
           m.lowp = 0;
           m.e = WEpi();
-          if (j == 1) m.e.alpha = mu_k;
-          if (j == p) {
-            m.e.D = b.M[mi ^ 1];
-            m.e.Nout = b.N[ni ^ 1];
-            m.e.np1 = (p + 1.0) / mu_n;  // N' = ((p+1)/mu' - M') mu'/p
-            m.e.inv_p = mu_n * inv_p;
-            m.e.pd = 1.0;
-          } else {
-            m.e.D = b.X[(j - 1) & 1];
-            src = m.e.D;
+          m.e.alpha = mu_k;
+          m.e.D = b.X[xb];
+          q[nq++] = m;
+          ProdDesc f;
+          f.L = P;
+          f.R = b.X[xb];
+          f.tri = 1;
+          f.lowp = 0;
+          f.e = WEpi();
+          last(f);
+          q[nq++] = f;
+        } else {
+          const double* src = b.M[mi];
+          for (int j = 1; j <= p; ++j) {
+            ProdDesc m;
+            m.L = b.N[ni];
+            m.R = src;
+            m.tri = 1;
+            m.lowp = 0;
+            m.e = WEpi();
+            if (j == 1) m.e.alpha = mu_k;
+            if (j == p) {
+              last(m);
+            } else {
+              m.e.D = b.X[(j - 1) & 1];
+              src = m.e.D;
+            }
+            q[nq++] = m;
           }
-          q[j] = m;
         }
       }
       __syncthreads();
-      rho = sqrt(run_products(q, p + 1, n, tile, &sm));
+      rho = sqrt(run_products(q, step_prods, n, tile, &sm));
       mu_k = mu_n;
       ci ^= 1;
       mi ^= 1;

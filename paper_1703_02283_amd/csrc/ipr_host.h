@@ -20,6 +20,10 @@ int fail(int code, const char* fmt, ...);
 // Copies `count` device doubles to host through a pinned buffer and waits.
 int read_scalars(const double* d, int count, double* host, hipStream_t stream);
 
+// Set while the allocation-free entry point runs on this thread: scalars are
+// read without the pinned buffer and no events are created.
+extern thread_local bool g_no_alloc;
+
 // For q(x) = b0 + b1 x + b2 x^2: *sup_phi = sup_{x in (0,1]} q(x)^p x and
 // *q_pos = 1 when q > 0 on all of (0, 1].
 void poly_guard(const double b[3], int p, double* sup_phi, int* q_pos);

@@ -63,7 +63,10 @@ __device__ void write_features(float* f, int n, int pm, double n1, double ninf,
   const double t1 = r.sd / s / n, t2 = r.sq / (s * s) / n;
   const double mean_d = r.sd / n;
   const double var_d = fmax(r.sd2 / n - mean_d * mean_d, 0.0);
-  f[0] = (float)(log2((double)n) / 10.0);
+  // the order enters clipped to the training sizes 64..1024: beyond them the
+  // network would extrapolate, and the iteration count depends on the
+  // spectrum, not on n
+  f[0] = (float)(fmin(fmax(log2((double)n), 6.0), 10.0) / 10.0);
   f[1] = (float)(pm / 4.0);
   f[2] = (float)t1;
   f[3] = (float)t2;
@@ -84,7 +87,7 @@ __device__ void write_features(float* f, int n, int pm, double n1, double ninf,
 // One workgroup per matrix. With s = sqrt(||A||_1 ||A||_inf), B = A / s,
 // d = diag B, r_i = sum_j |B_ij|, o_i = r_i - |d_i|, t1 = trace(B)/n,
 // t2 = ||B||_F^2 / n, the 16 features are
-//  0 log2(n)/10   1 p/4   2 t1   3 t2   4 log10 t1   5 log10 t2   6 t1^2/t2
+//  0 clamp(log2 n, 6, 10)/10   1 p/4   2 t1   3 t2   4 log10 t1   5 log10 t2   6 t1^2/t2
 //  7 min d   8 max d   9 log10 max(min d, 1e-30)   10 min (d_i - o_i)
 //  11 mean r   12 sum o / sum |d|   13 max_{i != j} |B_ij|   14 std(d)/mean(d)
 //  15 log10 s.

@@ -28,6 +28,7 @@
 #include "ipr_host.h"
 #include "scaling.h"
 #include "ipr_internal.h"
+#include "arith.h"
 #include "learned.h"
 #include "lowp.h"
 
@@ -54,7 +55,16 @@ static double* pinned_scalars() {
   return buf;
 }
 
+thread_local bool g_no_alloc = false;
+
 int read_scalars(const double* d, int count, double* host, hipStream_t stream) {
+  if (g_no_alloc) {
+    // no pinned buffer (its first use would allocate): a copy to pageable
+    // host memory, which the runtime stages itself
+    HIP_TRY(hipMemcpyAsync(host, d, count * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return IPR_OK;
+  }
   double* pin = pinned_scalars();
   if (!pin) return fail(IPR_EHIP, "hipHostMalloc of the scalar buffer failed");
   HIP_TRY(hipMemcpyAsync(pin, d, count * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -99,6 +109,27 @@ void poly_guard(const double b[3], int p, double* sup_phi, int* q_pos) {
   *q_pos = pos;
 }
 
+// Least value of phi(x) = q(x)^p x over [a, 1] for q(x) = b0 + b1 x + b2 x^2
+// positive there: at an end or at a root of (2p+1) b2 x^2 + (p+1) b1 x + b0
+// (where d/dx phi vanishes).
+double poly_min(const double b[3], int p, double a) {
+  auto phi = [&](double x) { return std::pow(b[0] + b[1] * x + b[2] * x * x, p) * x; };
+  double m = std::min(phi(a), phi(1.0));
+  const double aa = (2.0 * p + 1.0) * b[2], bb = (p + 1.0) * b[1], cc = b[0];
+  if (aa != 0.0) {
+    const double disc = bb * bb - 4 * aa * cc;
+    if (disc >= 0) {
+      const double sq = std::sqrt(disc);
+      for (double x : {(-bb + sq) / (2 * aa), (-bb - sq) / (2 * aa)})
+        if (x > a && x < 1.0) m = std::min(m, phi(x));
+    }
+  } else if (bb != 0.0) {
+    const double x = -cc / bb;
+    if (x > a && x < 1.0) m = std::min(m, phi(x));
+  }
+  return m;
+}
+
 }  // namespace ipr
 
 using namespace ipr;
@@ -135,6 +166,10 @@ int emul_digits(const ipr_schedule& s) {
 
 int n_mats(int p) { return p == 1 ? 5 : (p == 2 ? 6 : NMAT); }
 
+// Powers L^p by repeated squaring when p is a power of two >= 4 (fewer
+// products than p - 1 successive ones).
+bool binary_powers(int p) { return p >= 4 && (p & (p - 1)) == 0; }
+
 size_t carve(int n, int p, int dtype, int slices, bool store, Work* w, void* base, size_t cap,
              bool* ok) {
   Carver c(base, cap);
@@ -166,19 +201,26 @@ size_t carve(int n, int p, int dtype, int slices, bool store, Work* w, void* bas
   return c.used;
 }
 
+// Phase times from device events (none in the allocation-free entry point,
+// where every ms_* field stays 0).
 struct Timer {
-  hipEvent_t ev[8];
+  hipEvent_t ev[8] = {};
   hipStream_t s;
-  explicit Timer(hipStream_t st) : s(st) {
-    for (auto& e : ev) (void)hipEventCreate(&e);
+  bool on;
+  Timer(hipStream_t st, bool enabled) : s(st), on(enabled) {
+    if (on)
+      for (auto& e : ev) (void)hipEventCreate(&e);
   }
   ~Timer() {
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (on)
+      for (auto& e : ev) (void)hipEventDestroy(e);
   }
-  void mark(int i) { (void)hipEventRecord(ev[i], s); }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
   double ms(int a, int b) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+    if (!on || hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
     return t;
   }
 };
@@ -355,19 +397,39 @@ struct Solver {
     return e;
   }
 
-  // Mout = L^p B (p products, last with m_epilogue), t = triangle mode.
+  // Mout = L^p alpha1 B (last product with m_epilogue), t = triangle mode.
+  // For p a power of two >= 4 by binary powering: P = L^(p/2) from repeated
+  // squaring, then P (P B), log2(p) + 1 products (3 instead of 4 for p = 4);
+  // otherwise L (L (... (L B))), p products.
   int power_chain(const double* L, const double* B, double* Mout, double* Nout, int t,
                   double alpha1 = 1.0) {
-    const double* src = B;
-    for (int j = 1; j <= p; ++j) {
-      Epilogue e;
-      if (j == p)
-        e = m_epilogue(Mout, Nout);
-      else
-        e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
-      if (j == 1) e.alpha = alpha1;
-      TRY(prod(L, src, t, e));
-      src = e.D;
+    if (binary_powers(p)) {
+      const double* P = L;
+      int xb = 0;  // X[0] and X[1] alternate (both exist for p >= 3)
+      for (int q = 1; 2 * q <= p / 2; q *= 2) {
+        Epilogue e;  // L^(2q) = L^q L^q
+        e.D = X[xb];
+        TRY(prod(P, P, t, e));
+        P = e.D;
+        xb ^= 1;
+      }
+      Epilogue e;  // T = P alpha1 B
+      e.D = X[xb];
+      e.alpha = alpha1;
+      TRY(prod(P, B, t, e));
+      TRY(prod(P, e.D, t, m_epilogue(Mout, Nout)));
+    } else {
+      const double* src = B;
+      for (int j = 1; j <= p; ++j) {
+        Epilogue e;
+        if (j == p)
+          e = m_epilogue(Mout, Nout);
+        else
+          e.D = X[(j - 1) & 1];  // j < p: X[0] for j = 1, X[1] exists when p >= 3
+        if (j == 1) e.alpha = alpha1;
+        TRY(prod(L, src, t, e));
+        src = e.D;
+      }
     }
     if (!t) {
       TRY(symmetrize(Mout, n, st));
@@ -467,12 +529,24 @@ struct Solver {
   // triangle products (when enabled), then one full product C^p A.
   int true_residual(double* tau) {
     const double* P = C();
-    for (int j = 2; j <= p; ++j) {
-      Epilogue e;
-      e.D = X[j & 1];  // X[0] for C^2, X[1] (p >= 3) for C^3, ...
-      TRY(prod.f64(C(), P, tri, e));
-      if (!tri) TRY(symmetrize(e.D, n, st));
-      P = e.D;
+    if (binary_powers(p)) {
+      int xb = 0;
+      for (int q = 1; q < p; q *= 2) {  // C^(2q) = C^q C^q
+        Epilogue e;
+        e.D = X[xb];
+        TRY(prod.f64(P, P, tri, e));
+        if (!tri) TRY(symmetrize(e.D, n, st));
+        P = e.D;
+        xb ^= 1;
+      }
+    } else {
+      for (int j = 2; j <= p; ++j) {
+        Epilogue e;
+        e.D = X[j & 1];  // X[0] for C^2, X[1] (p >= 3) for C^3, ...
+        TRY(prod.f64(C(), P, tri, e));
+        if (!tri) TRY(symmetrize(e.D, n, st));
+        P = e.D;
+      }
     }
     Epilogue e;
     e.alpha = -1.0;
@@ -526,6 +600,19 @@ struct Solver {
     return IPR_OK;
   }
 
+  // Iterate k's entries of the caller's history arrays: rho = ||I - M_k||_F
+  // and, with a reference matrix, ||C_k - ref||_F (one pass over C_k).
+  int record_hist(const ipr_schedule& s, int k, double rho) {
+    if (k < 0 || k >= s.hist_len) return IPR_OK;
+    if (s.hist_rho) s.hist_rho[k] = rho;
+    if (s.hist_ref && s.hist_err) {
+      TRY(diff_rows(C(), s.hist_ref, n, w.norms_scratch, st));
+      TRY(reduce_fro(w.norms_scratch, n, w.scal + 10, st));
+      if (int rc = read_scalars(w.scal + 10, 1, &s.hist_err[k], st)) return rc;
+    }
+    return IPR_OK;
+  }
+
   // M_k = C_k^p A (and N_k) from C_k, or R_k = I - A C_k in Newton-Schulz mode.
   int recompute(bool ns) {
     if (ns) {
@@ -541,6 +628,86 @@ struct Solver {
     return power_chain(C(), A, M(), Nb[ni], 0);
   }
 };
+
+// The all-arithmetic regime (schedule.store_regime = 1): the coupled
+// iteration from the scaled identity with every scalar operation rounded to
+// the custom type (arith.hip). The stopping rules are the FP64 loop's; the
+// final check ||I - C^p A||_F runs in FP64 against the caller's A.
+int solve_arith(Solver& sv, const ipr_schedule& s, double tol, double sigma, ipr_result& res) {
+  const int n = sv.n, p = sv.p, fmt = s.store_format, bits = s.store_bits;
+  hipStream_t st = sv.st;
+  const double c = round_store(std::pow(sigma, -1.0 / p), fmt, bits);
+  const double cp = round_store(std::pow(c, (double)p), fmt, bits);
+  HIP_TRY(arith_start(sv.Atrue, n, c, cp, fmt, bits, sv.C(), sv.M(), st));
+  HIP_TRY(arith_next(sv.M(), n, p, fmt, bits, sv.Nb[sv.ni], sv.w.partial, st));
+  sv.slots = n;
+  if (int rc = sv.reduce()) return rc;
+  res.init_scale = sigma;
+  res.init_bound = 1.0;
+  res.poly_used[0] = 1.0;
+  double best = std::numeric_limits<double>::infinity(), last_tau = best, rho = 0.0;
+  int stale = 0, failed_verify = 0, status = IPR_EMAXITER, k = 0, verified_at = -1;
+  for (k = 0;; ++k) {
+    if (int rc = read_scalars(sv.rho_dev(), 1, &rho, st)) return rc;
+    res.residual_proxy = rho;
+    if (int rc = sv.record_hist(s, k, rho)) return rc;
+    if (!std::isfinite(rho) || rho > 1e6) {
+      status = IPR_EDIVERGED;
+      break;
+    }
+    bool floor = false;
+    if (rho < tol && s.verify) {
+      double tau;
+      if (int rc = sv.true_residual(&tau)) return rc;
+      res.residual_true = tau;
+      verified_at = k;
+      if (tau < tol) {
+        status = IPR_OK;
+        break;
+      }
+      floor = ++failed_verify >= 2 && !(tau < 0.5 * last_tau);
+      last_tau = tau;
+    } else if (rho < tol) {
+      status = IPR_OK;
+      break;
+    }
+    if (rho < 1.0) {
+      if (rho < s.stall_ratio * best) {
+        best = rho;
+        stale = 0;
+      } else if (++stale >= 3) {
+        floor = true;
+      }
+    }
+    if (floor) {
+      status = IPR_EFLOOR;
+      break;
+    }
+    if (k >= s.max_iter) break;
+    // C_{k+1} = C_k N_k, M_{k+1} = N_k (N_k (... (N_k M_k))), N_{k+1}
+    double* Nc = sv.Nb[sv.ni];
+    HIP_TRY(gemm_arith(sv.C(), Nc, sv.Cb[sv.ci ^ 1], n, fmt, bits, st));
+    const double* src = sv.M();
+    for (int j = 1; j <= p; ++j) {
+      double* dst = j == p ? sv.Mb[sv.mi ^ 1] : sv.X[(j - 1) & 1];
+      HIP_TRY(gemm_arith(Nc, src, dst, n, fmt, bits, st));
+      src = dst;
+    }
+    sv.prod.gemms += p + 1;
+    sv.ci ^= 1;
+    sv.mi ^= 1;
+    HIP_TRY(arith_next(sv.M(), n, p, fmt, bits, Nc, sv.w.partial, st));
+    sv.slots = n;
+    if (int rc = sv.reduce()) return rc;
+  }
+  res.iters_fp64 = k;
+  if (status != IPR_OK && status != IPR_EDIVERGED && s.verify && verified_at != k) {
+    double tau;
+    if (int rc = sv.true_residual(&tau)) return rc;
+    res.residual_true = tau;
+  }
+  return status;
+}
 
 }  // namespace
 
@@ -676,6 +843,11 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       return fail(IPR_EARG, "ipr_solve: approximate storage runs the plain coupled iteration "
                   "from the scaled identity in FP64 (no squarings, no scaled steps)");
   }
+  if (s.store_regime < 0 || s.store_regime > 1)
+    return fail(IPR_EARG, "ipr_solve: unknown store_regime %d", s.store_regime);
+  if (s.store_regime == 1 && !store)
+    return fail(IPR_EARG, "ipr_solve: the all-arithmetic regime needs a store_format");
+  if (s.hist_len < 0) return fail(IPR_EARG, "ipr_solve: hist_len < 0");
   if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
     return fail(IPR_EARG, "ipr_solve: the learned start needs schedule.mlp_params");
 
@@ -707,7 +879,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   sv.X[1] = p >= 3 ? w.m[6] : nullptr;
   sv.Rns = w.m[2];  // Newton-Schulz (p = 1) does not carry M
   const size_t nn = (size_t)n * n;
-  Timer tm(stream);
+  Timer tm(stream, !g_no_alloc);
 
   // ---- norms of eq. (3)
   tm.mark(0);
@@ -721,6 +893,23 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   tm.mark(1);
   if (!(s2 > 0.0) || !std::isfinite(s2))
     return fail(IPR_EARG, "ipr_solve: A has zero or non-finite norm");
+
+  if (store && s.store_regime == 1) {
+    const int status = solve_arith(sv, s, tol, sigma, res);
+    if (status == IPR_EHIP || status == IPR_EARG) return status;
+    tm.mark(4);
+    if (sv.C() != dC) HIP_TRY(copy(sv.C(), nn, dC, stream));
+    tm.mark(5);
+    HIP_TRY(hipStreamSynchronize(stream));
+    res.ms_norms = tm.ms(0, 1);
+    res.ms_refine = tm.ms(1, 4);
+    res.ms_verify = tm.ms(4, 5);
+    res.status = status;
+    res.gemms = sv.prod.gemms;
+    sv.prod.totals(0, &res.gemm_launches, &res.ms_gemm, &res.gemm_flops);
+    if (out) *out = res;
+    return status;
+  }
 
   // ---- start C_0 = sc^{-1/p} q(A / sc), q(x) = b0 + b1 x + b2 x^2, with the
   // spectrum of A / sc inside (0, 1]; then M_0 = C_0^p A and N_0.
@@ -825,13 +1014,17 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
 
   // Dynamically scaled iteration: bounds [mod_a, mod_b] on the spectrum of
   // M_k are carried through the scalar map of a step; each step k multiplies
-  // M_k by mu_k >= 1 (C_k by mu_k^{1/p}), chosen to lift the lower end. The
-  // lower end starts from a Lanczos estimate of lambda_min (from above: an
-  // overestimate only makes the factors smaller); the upper end 1 is certified
-  // by the start, and mu_k mod_b < 2 keeps every step inside eq. (2). Once the
-  // residual is below 1 it bounds both ends, and from a lower end of 1/2 on
-  // the steps are unscaled. mu_0 is folded into the start's scale.
-  bool dyn = s.dynamic_scaling && init == IPR_INIT_IDENTITY &&
+  // M_k by mu_k >= 1 (C_k by mu_k^{1/p}), chosen to lift the lower end. With
+  // the start C_0 = sc^{-1/p} q(A / sc) (the scaled identity: q = 1) the
+  // eigenvalues of M_0 are phi(x) = q(x)^p x at x = lambda / sc in (0, 1]:
+  // the upper end is sup phi on (0, 1] (certified), the lower end the least
+  // phi on [theta / sc, 1], theta a Lanczos estimate of lambda_min (from
+  // above: an overestimate only makes the factors smaller). mu_k mod_b < 2
+  // keeps every step inside eq. (2). Once the residual is below 1 it bounds
+  // both ends, and from a lower end of 1/2 on the steps are unscaled. mu_0
+  // is folded into the start (q -> mu_0^{1/p} q).
+  bool dyn = s.dynamic_scaling &&
+             (init == IPR_INIT_IDENTITY || init == IPR_INIT_LEARNED || init == IPR_INIT_POLY) &&
              (s.bulk_dtype == IPR_FP64 || s.bulk_dtype == IPR_FP64_INT8_EMUL) &&
              s.evaluation == IPR_EVAL_COUPLED && n >= 32;
   double mod_a = 0.0, mod_b = 1.0, mu_k = 1.0;
@@ -839,14 +1032,19 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     double theta = 0.0;
     if (int rc = sv.lanczos_min(std::min(24, n - 8), w.m[0], &theta)) return rc;
     res.lmin_est = theta;
-    dyn = theta > 0.0 && std::isfinite(theta);
+    dyn = theta > 0.0 && std::isfinite(theta) && std::isfinite(sup_phi) && sup_phi > 0.0;
     if (dyn) {
-      mod_a = std::min(theta / sc, 1.0);
-      const double mu0 = choose_mu(mod_a, 1.0, p);
-      sc /= mu0;
-      mod_a *= mu0;
-      mod_b = mu0;
-      res.init_bound = mu0;  // sup of C_0^p lambda over the spectrum bound
+      const double lo = poly_min(b, p, std::min(theta / sc, 1.0));
+      dyn = lo > 0.0;
+      if (dyn) {
+        const double mu0 = choose_mu(lo, sup_phi, p);
+        const double t = std::pow(mu0, 1.0 / p);
+        for (double& v : b) v *= t;
+        mod_a = lo * mu0;
+        mod_b = sup_phi * mu0;
+        res.init_bound = mod_b;  // sup of C_0^p lambda over the spectrum bound
+        for (int i = 0; i < 3; ++i) res.poly_used[i] = b[i];
+      }
     }
   }
 
@@ -895,7 +1093,11 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
 
   // ---- iterations: optional low-precision bulk phase, then FP64
   // (int8-slice products are FP64-accurate: no low-precision phase)
-  const bool lowp = s.bulk_dtype != IPR_FP64 && s.bulk_dtype != IPR_FP64_INT8_EMUL;
+  // A bf16 / fp16 / fp8 phase for p >= 2 would end in the FP64 restart (its
+  // error does not commute with A): skipped unless forced.
+  const bool lp_dtype = s.bulk_dtype != IPR_FP64 && s.bulk_dtype != IPR_FP64_INT8_EMUL;
+  const bool lowp = lp_dtype && (p == 1 || s.bulk_force);
+  res.bulk_skipped = lp_dtype && !lowp ? 1 : 0;
   bool lp_restart = false;
   int status = IPR_EMAXITER;
   int k = 0, kb = 0;
@@ -1038,13 +1240,14 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   bool ns = (lowp && p == 1 && !lp_restart) || ns_order;
   double best = std::numeric_limits<double>::infinity();
   int stale = 0, failed_verify = 0, verified_at = -1;
-  bool short_failed = false, reestimated = false;
+  bool short_failed = false, reestimated = false, div_restart = false;
   double last_tau = std::numeric_limits<double>::infinity();
   double prev = std::numeric_limits<double>::infinity();
   const int kmax = s.max_iter - res.iters_bulk;
   for (k = 0;; ++k) {
     if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
     res.residual_proxy = rho;
+    if (int rc = sv.record_hist(s, k, rho)) return rc;
     const bool bad = !std::isfinite(rho) || rho > 1e6;
     if (dyn && rho < 1.0) {  // ||I - M_k||_2 <= rho bounds the spectrum of M_k
       mod_a = std::max(mod_a, 1.0 - rho);
@@ -1086,6 +1289,24 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       best = last_tau = prev = std::numeric_limits<double>::infinity();
       stale = failed_verify = 0;
       verified_at = -1;
+      --k;  // no step was taken
+      continue;
+    }
+    if (bad && !lp_restart && !div_restart && !store) {
+      // Divergence (an eq. (3) start outside eq. (2)'s region that the guard
+      // let through, a caller's start, rounding): one restart from the scaled
+      // identity at the norm bound, with plain steps. A second divergence
+      // (e.g. an indefinite A) is reported.
+      div_restart = true;
+      dyn = false;
+      ns = ns_order;
+      if (int rc = restart_identity()) return rc;
+      if (ns_order)
+        if (int rc = sv.recompute(true)) return rc;
+      best = last_tau = prev = std::numeric_limits<double>::infinity();
+      stale = failed_verify = 0;
+      verified_at = -1;
+      short_failed = false;
       --k;  // no step was taken
       continue;
     }
@@ -1141,6 +1362,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
         (p + 1.0) / (2.0 * p) * rho * rho < tol && k < kmax) {
       if (int rc = sv.step(false, false)) return rc;
       ++k;
+      if (int rc = sv.record_hist(s, k, std::numeric_limits<double>::quiet_NaN())) return rc;
       double tau;
       if (int rc = sv.true_residual(&tau)) return rc;
       res.residual_true = tau;

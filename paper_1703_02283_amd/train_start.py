@@ -94,12 +94,18 @@ def guard_ok(b, p):
 
 
 def candidates(p):
-    """Candidate starts of the label search, all satisfying eq. (2) on (0, 1]."""
+    """Candidate starts of the label search, all satisfying eq. (2) on (0, 1]:
+    constant, linear and quadratic q (a quadratic term costs the solver no
+    more than a linear one: A^2 is formed for the scale anyway, and either
+    needs the p products of M_0)."""
     out = []
     for b0 in np.geomspace(0.5, 2.0 ** (1.0 / p) * 0.999, 28):
         out.append((b0, 0.0, 0.0))
         for t in (0.25, 0.5, 0.75):
             out.append((b0, -t * b0, 0.0))
+        for t in (0.5, 0.75, 1.0):
+            for u in (0.15, 0.3):
+                out.append((b0, -t * b0, u * b0))
     return np.array([c for c in out if guard_ok(c, p)])
 
 
@@ -119,11 +125,22 @@ def build_dataset(items, device, chunk=256):
     cands = {p: candidates(p) for p in (1, 2, 3, 4)}
     t0 = time.time()
     done = 0
+    phase = {"matrices": 0.0, "features": 0.0, "scales": 0.0, "labels": 0.0}
+    ws_norms = torch.empty(8 * (1024 * (1024 // 256 + 4) + 64), dtype=torch.uint8, device=device)
+    g_buf = None
+
+    def tick(name, t):
+        torch.cuda.synchronize()
+        now = time.time()
+        phase[name] += now - t
+        return now
     for n, idx in sorted(order.items()):
         for c0 in range(0, len(idx), chunk):
             sel = idx[c0:c0 + chunk]
             its = [items[k] for k in sel]
+            t = time.time()
             a, lams = make_group(its, device)
+            t = tick("matrices", t)
             b = len(its)
             flat = a.reshape(-1)
             offs = [j * n * n for j in range(b)]
@@ -131,18 +148,23 @@ def build_dataset(items, device, chunk=256):
             ps = [it[1] for it in its]
             f = ipr.ipr_features(flat, offs, ns, ps)
             feats[sel] = f.cpu().numpy()
-            # certified scale and the norm scale
-            absa = a.abs()
-            n1 = absa.sum(-2).amax(-1)
-            ni = absa.sum(-1).amax(-1)
-            a2 = torch.matmul(a, a).abs()
-            g1 = a2.sum(-2).amax(-1)
-            gi = a2.sum(-1).amax(-1)
-            sig = torch.sqrt(n1 * ni).cpu().numpy()
-            bound = torch.sqrt(torch.sqrt(g1 * gi)).cpu().numpy() * (1 + 8 * n * 2.2e-16)
+            t = tick("features", t)
+            # certified scale and the norm scale, by the library's kernels (the
+            # solver's own norms and FP64 product)
+            sig = np.zeros(b)
+            bound = np.zeros(b)
+            if g_buf is None or g_buf.shape[0] != n:
+                g_buf = torch.empty((n, n), dtype=torch.float64, device=device)
+            for j in range(b):
+                n1, ni = ipr.ipr_norms(a[j], workspace=ws_norms)
+                ipr.ipr_gemm(a[j], a[j], triangle=True, out=g_buf)
+                g1, gi = ipr.ipr_norms(g_buf, workspace=ws_norms)
+                sig[j] = math.sqrt(n1 * ni)
+                bound[j] = math.sqrt(math.sqrt(g1 * gi)) * (1 + 8 * n * 2.0 ** -52)
             sc = np.minimum(sig, bound)
             scales[sel] = sc
             sigmas[sel] = sig
+            t = tick("scales", t)
             lam_flat = torch.tensor(np.concatenate(lams), dtype=torch.float64, device=device)
             loffs = [j * n for j in range(b)]
             for pv in sorted(set(ps)):
@@ -163,9 +185,11 @@ def build_dataset(items, device, chunk=256):
                     labels[gj] = (math.log(bb[0]), bb[1], bb[2])
                     best_products[gj] = cost[r, k[r]]
                     ident_products[gj] = (pv + 1) * ident[r]
+            tick("labels", t)
             done += b
             del a
-        log(f"n={n}: {done}/{m} items, {time.time() - t0:.0f} s")
+        log(f"n={n}: {done}/{m} items, {time.time() - t0:.0f} s, phases "
+            + ", ".join(f"{k} {v:.0f} s" for k, v in phase.items()))
     return dict(feats=feats, labels=labels, scales=scales, sigmas=sigmas,
                 best_products=best_products, ident_products=ident_products)
 

@@ -111,7 +111,9 @@ def test_batched_bf16_bulk_for_p1(ipr):
         assert r.status == ipr.IPR_OK, r.as_dict()
         assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
         if p == 1:
-            assert r.iters_bulk > 0
+            assert r.iters_bulk > 0 and r.bulk_skipped == 0
+        else:                          # the bf16 phase runs for p = 1 items only
+            assert r.iters_bulk == 0 and r.bulk_skipped == 1
 
 
 def test_batched_bf16_bulk_restarts_in_fp64(ipr):

@@ -166,24 +166,82 @@ def test_learned_start_uses_the_batched_features(ipr, n):
 
 @pytest.mark.skipif(_weights() is None, reason="no trained weights in the package")
 def test_learned_start_gains_on_heldout_sample(ipr):
+    # every item counts, solved or not: where the learned start fails and the
+    # identity succeeds, the solve would be repeated from the identity, so
+    # the identity's products are added to the learned start's (items where
+    # both fail, at condition numbers whose 1e-10 lies below the FP64 floor,
+    # count their own products); device time of both starts is reported
     import torch
     from paper_1703_02283_amd import train_start as ts
     theta = torch.tensor(_weights()).cuda()
     items = ts.recipe(60, 3 * 10**6, n_range=(64, 400))
     tot_i = tot_l = 0
-    fallbacks = 0
+    ms_i = ms_l = 0.0
+    fallbacks = fail_i = fail_l = 0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for (n, p, kappa, seed) in items:
         a, lam = w.batch_matrix(n, kappa, seed)
         A = dev(a)
-        _, ri = ipr.ipr_solve(A, p, 1e-10)
         s = ipr.ipr_schedule_default(init=ipr.IPR_INIT_LEARNED, mlp_params=theta)
+        ev[0].record()
+        _, ri = ipr.ipr_solve(A, p, 1e-10)
+        ev[1].record()
         C, rl = ipr.ipr_solve(A, p, 1e-10, schedule=s)
-        ok = (ri.status == ipr.IPR_OK) and (rl.status == ipr.IPR_OK)
-        if ok:
+        ev[2].record()
+        torch.cuda.synchronize()
+        ms_i += ev[0].elapsed_time(ev[1])
+        ms_l += ev[1].elapsed_time(ev[2])
+        tot_i += ri.gemms
+        loss = rl.status != ipr.IPR_OK and ri.status == ipr.IPR_OK
+        tot_l += rl.gemms + (ri.gemms if loss else 0)
+        fail_i += ri.status != ipr.IPR_OK
+        fail_l += rl.status != ipr.IPR_OK
+        if rl.status == ipr.IPR_OK:
             assert it.rel_fro(host(C), it.eig_root(a, p)) <= 1e-10
-            tot_i += ri.gemms
-            tot_l += rl.gemms
         fallbacks += rl.fallback_used
-    say("products identity", tot_i, "learned", tot_l, "fallbacks", fallbacks)
+    say("products identity", tot_i, "learned", tot_l, "fallbacks", fallbacks,
+        "failed identity", fail_i, "learned", fail_l, "ms identity", ms_i, "learned", ms_l)
     assert tot_l < 0.97 * tot_i
+    assert fail_l <= fail_i
     assert fallbacks <= len(items) // 10
+
+
+@pytest.mark.skipif(_weights() is None, reason="no trained weights in the package")
+@pytest.mark.parametrize("n,kappa,seed,p", [(300, 1e4, 5, 2), (500, 1e3, 6, 3), (400, 3e4, 7, 1)])
+def test_learned_start_with_scaled_steps(ipr, n, kappa, seed, p):
+    # The learned start combined with scaled steps. The oracle builds the
+    # start on its own (its features and network on the stored weights, the
+    # 5% rule, eq. (2)'s rescale, the certified bound from A^2 by numpy) and
+    # runs the scaled iteration from the exact spectrum: the same root, the
+    # library's polynomial proportional to the oracle's (the library folds
+    # the first factor mu_0^{1/p} into it), and its count within -1..+2.
+    import torch
+    from oracle import guard, mlp
+    th = _weights()
+    a, lam = w.batch_matrix(n, kappa, seed)
+    s = ipr.ipr_schedule_default(init=ipr.IPR_INIT_LEARNED, dynamic_scaling=1,
+                                 mlp_params=torch.tensor(th).cuda())
+    C, r = ipr.ipr_solve(dev(a), p, 1e-10, schedule=s)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 0, r.as_dict()
+    assert it.rel_fro(host(C), it.eig_root(a, p)) <= 1e-10
+    y = mlp.forward(th.astype(np.float64), ft.features(a, p)[None, :])[0][0]
+    b = np.array([np.exp(y[0]), y[1], y[2]])
+    if abs(b[1]) < 0.05 * b[0] and abs(b[2]) < 0.05 * b[0]:
+        b[1] = b[2] = 0.0
+    ok, sup, _ = guard.check(b, p)
+    if sup >= 2.0:
+        b = b * (1.98 / sup) ** (1.0 / p)
+    a2 = a @ a
+    sigma = np.sqrt(it.norm_1(a) * it.norm_inf(a))
+    sc = min(sigma, np.sqrt(np.sqrt(it.norm_1(a2) * it.norm_inf(a2))) * (1 + 8 * n * 2.0 ** -52))
+    assert abs(r.init_scale - sc) <= 1e-12 * sc
+    used = np.array(list(r.poly_used))
+    t = used[0] / b[0]
+    assert np.allclose(used, t * b, rtol=1e-4, atol=1e-5 * used[0])
+    ref = it.solve(a, p, 1e-10, init="poly", poly=tuple(b), scaled=sc)
+    r0 = ipr.ipr_solve(dev(a), p, 1e-10, schedule=ipr.ipr_schedule_default(
+        init=ipr.IPR_INIT_LEARNED, mlp_params=torch.tensor(th).cuda()))[1]
+    say("learned + scaled: iterations", r.iters_fp64, "oracle", ref.iters,
+        "learned unscaled", r0.iters_fp64, "poly", used)
+    assert ref.status == it.OK and -1 <= r.iters_fp64 - ref.iters <= 2
+    assert r.iters_fp64 < r0.iters_fp64

@@ -90,11 +90,22 @@ def test_solve_rejects_bad_sizes_and_aliasing():
 def test_int8_slice_product_rejects_bad_arguments_before_any_device_call():
     f = binding._fn("ipr_gemm_emul")
     D = ct.c_void_p(1 << 20)
-    for slices in (0, 13):
-        assert f(FAKE_A, FAKE_C, D, 64, slices, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
-    assert f(FAKE_A, FAKE_C, FAKE_A, 64, 10, FAKE_W, 1 << 40, None) == ipr.IPR_EARG   # alias
-    assert f(FAKE_A, FAKE_C, D, 200000, 10, FAKE_W, 1 << 40, None) == ipr.IPR_EARG    # n too large
-    assert f(FAKE_A, FAKE_C, D, 64, 10, FAKE_W, 16, None) == ipr.IPR_EARG            # workspace
+    for tri in (0, 1):
+        for slices in (0, 13):
+            assert f(FAKE_A, FAKE_C, D, 64, slices, tri, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
+        assert f(FAKE_A, FAKE_C, FAKE_A, 64, 10, tri, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
+        assert f(FAKE_A, FAKE_C, D, 200000, 10, tri, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
+        assert f(FAKE_A, FAKE_C, D, 64, 10, tri, FAKE_W, 16, None) == ipr.IPR_EARG
+
+
+def test_low_precision_product_rejects_bad_arguments_before_any_device_call():
+    f = binding._fn("ipr_gemm_lowp")
+    D = ct.c_void_p(1 << 20)
+    for tri in (0, 1):
+        for dtype in (0, 4, 7):                     # FP64, INT8 emulation, unknown
+            assert f(FAKE_A, FAKE_C, D, 64, dtype, tri, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
+        assert f(FAKE_A, FAKE_C, FAKE_A, 64, 1, tri, FAKE_W, 1 << 40, None) == ipr.IPR_EARG
+        assert f(FAKE_A, FAKE_C, D, 64, 1, tri, FAKE_W, 16, None) == ipr.IPR_EARG
 
 
 def test_lowdin_rejects_aliasing_and_short_workspace():

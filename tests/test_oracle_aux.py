@@ -94,7 +94,9 @@ def test_features_on_hand_matrix():
     sigma = 5.0                       # ||A||_1 = ||A||_inf = 5
     b = a / sigma
     assert f.shape == (16,)
-    assert f[0] == math.log2(3) / 10 and f[1] == 0.5
+    assert f[0] == 0.6 and f[1] == 0.5            # order clipped up to 2^6 (training sizes)
+    assert ft.features(np.eye(128), 1)[0] == 0.7
+    assert ft.features(np.eye(2048), 1)[0] == 1.0   # and down to 2^10
     assert abs(f[2] - 9.0 / 5 / 3) < 1e-15                       # trace/sigma/n
     assert abs(f[3] - (16 + 9 + 4 + 4 * 1) / 25 / 3) < 1e-15      # ||B||_F^2 / n
     assert abs(f[7] - 0.4) < 1e-15 and abs(f[8] - 0.8) < 1e-15
@@ -202,6 +204,20 @@ def test_scaled_iteration_reaches_the_root_in_fewer_steps():
             for x, y in zip(r.rho, rho):
                 if y > 1e-6:
                     assert abs(x - y) <= 1e-8 * y
+
+
+def test_scaled_iteration_from_a_polynomial_start():
+    # C_0 = s^{-1/p} q(A/s) with q(x) = b0 + b1 x: the dense count equals the
+    # per-eigenvalue count, and the iteration reaches the root
+    import workloads as w
+    from oracle import iteration as it
+    a, lam, _ = w.spd_log_spectrum(100, 1e3, seed=81)
+    for p, b in ((1, (1.2, -0.4, 0.0)), (2, (1.1, -0.3, 0.05)), (3, (1.0, -0.2, 0.0))):
+        s = it.power_scale(a, p, 6, True)[0]
+        r = it.solve(a, p, 1e-10, init="poly", poly=b, scaled=s)
+        k, _, _ = it.scaled_spectral_count(lam, p, s, 1e-10, poly=b)
+        assert r.status == it.OK and r.iters == k
+        assert it.rel_fro(r.c, it.eig_root(a, p)) < 1e-11
 
 
 def test_scaled_iteration_on_diagonal_matrices_is_the_scalar_recursion():
