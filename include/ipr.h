@@ -214,6 +214,24 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol,
               const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
               hipStream_t stream);
 
+/* Size of the fixed device workspace of ipr_solve_noalloc: 64 MiB per device. */
+#define IPR_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* ipr_solve without a caller workspace, for callers that cannot allocate
+ * device memory (serving loops, harnesses that forbid hipMalloc). The
+ * workspace is a fixed 64 MiB device array of the library, one per device,
+ * looked up on the first call on each device and held until the process
+ * ends. The call allocates nothing: no device or pinned memory, no events.
+ * Arguments and results as ipr_solve, except:
+ *   - ipr_workspace_size(n, p, 1, s) must not exceed IPR_NOALLOC_SCRATCH_BYTES
+ *     (n <= 1094 with the FP64 schedules); larger problems return IPR_EARG;
+ *   - schedule.timing must be 0 (IPR_EARG otherwise); every ms_* field is 0.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (the solve initialises all it reads): calls that overlap in
+ * time on one device race, whatever their streams. */
+int ipr_solve_noalloc(const double* dA, double* dC, int n, int p, double tol,
+                      const ipr_schedule* s, ipr_result* out, hipStream_t stream);
+
 /* Independent solves of `batch` SPD matrices of uneven orders in one
  * persistent kernel launch (device-side iteration loop per matrix).
  *   dA_packed, dC_packed  device, matrices back to back (float64)

@@ -105,6 +105,8 @@ _SIGS = {
                                        ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_double,
                                        ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                                        ct.c_void_p]),
+    "ipr_solve_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_double,
+                                     ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "ipr_get_batched_tiles": (ct.c_int, [ct.c_void_p]),
     "ipr_set_batched_tiles": (ct.c_int, [ct.c_void_p]),
 }
@@ -211,6 +213,31 @@ def ipr_solve(A, p, tol, schedule=None, out=None, workspace=None, stream=None,
     res = IprResult()
     rc = _fn("ipr_solve")(_ptr(A), _ptr(C), n, p, tol, ct.byref(sch), ct.byref(res),
                           _ptr(ws), ws.numel(), _stream(stream))
+    if rc in raise_on:
+        raise IprError(rc, ipr_last_error())
+    return C, res
+
+
+IPR_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ipr_solve_noalloc(A, p, tol, schedule=None, out=None, stream=None,
+                      raise_on=(IPR_EARG, IPR_EHIP, IPR_EGUARD)):
+    """ipr_solve on the library's fixed device scratch instead of a caller
+    workspace (see include/ipr.h). ``out`` (n x n float64 device tensor) is
+    the caller's output buffer; the call itself allocates nothing."""
+    _need(A, torch.float64, name="A")
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n:
+        raise ValueError("A must be square")
+    sch = schedule if schedule is not None else ipr_schedule_default()
+    if sch.init == IPR_INIT_USER and out is None:
+        raise ValueError("init=IPR_INIT_USER takes C_0 in `out`")
+    C = out if out is not None else torch.empty_like(A)
+    _need(C, torch.float64, (n, n), "out")
+    res = IprResult()
+    rc = _fn("ipr_solve_noalloc")(_ptr(A), _ptr(C), n, p, tol, ct.byref(sch), ct.byref(res),
+                                  _stream(stream))
     if rc in raise_on:
         raise IprError(rc, ipr_last_error())
     return C, res
