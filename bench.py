@@ -348,7 +348,7 @@ def lowdin_runs(ipr, torch, w, dev, tol):
     """The step after the inverse square root in the paper's application:
     S^{-1/2} H S^{-1/2} for the n = 4096 overlap matrix and a Hamiltonian-like
     matrix of the same Gaussian basis (ipr_lowdin: the p = 2 solve plus two
-    FP64 products)."""
+    FP64 products), then its eigenvalues (ipr_eigvalsh)."""
     n = 4096
     s, h = w.overlap_and_hamiltonian(n, seed=0)
     S, H = torch.from_numpy(s).to(dev), torch.from_numpy(h).to(dev)
@@ -367,7 +367,18 @@ def lowdin_runs(ipr, torch, w, dev, tol):
                      "residual_true": r.residual_true,
                      "asymmetry": float((Ht - Ht.T).abs().max())}
         log(f"lowdin {name}", json.dumps(out[name]))
-    del S, H
+    # the eigenvalues of X H X (those of H c = e S c): Householder
+    # tridiagonalisation and bisection on the GPU
+    ipr.ipr_eigvalsh(Ht)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ev = ipr.ipr_eigvalsh(Ht)
+    torch.cuda.synchronize()
+    out["eigenvalues_of_XHX"] = {"seconds": time.perf_counter() - t,
+                                 "lowest": float(ev[0]), "highest": float(ev[-1]),
+                                 "ascending": bool((ev[1:] >= ev[:-1]).all())}
+    log("lowdin eigenvalues", json.dumps(out["eigenvalues_of_XHX"]))
+    del S, H, X, Ht
     torch.cuda.empty_cache()
     return out
 

@@ -214,6 +214,20 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol,
               const ipr_schedule* s, ipr_result* out, void* dWork, size_t work_bytes,
               hipStream_t stream);
 
+/* Eigenvalues of a dense symmetric matrix, ascending: the step after the
+ * Loewdin transform (Section IV-A: the eigenvalues of X H X, X = S^{-1/2},
+ * are those of H c = e S c). Householder reduction to tridiagonal form (one
+ * reflector per column, the trailing matrix kept whole) and bisection on the
+ * Sturm count of the tridiagonal matrix, FP64 throughout.
+ *   dA    device, n x n float64, symmetric (read only)
+ *   dW    device, n float64: the eigenvalues in ascending order
+ *   dWork device workspace of work_bytes >= ipr_eigvalsh_workspace(n)
+ * Errors: IPR_EARG for a null pointer, n < 1 or a short workspace. Stream
+ * ordered; returns without synchronising. */
+int ipr_eigvalsh(const double* dA, int n, double* dW, void* dWork, size_t work_bytes,
+                 hipStream_t stream);
+size_t ipr_eigvalsh_workspace(int n);
+
 /* Size of the fixed device workspace of ipr_solve_noalloc: 64 MiB per device. */
 #define IPR_NOALLOC_SCRATCH_BYTES (64u << 20)
 

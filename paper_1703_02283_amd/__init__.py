@@ -14,7 +14,7 @@ from .binding import (  # noqa: F401
     IPR_STORE_NONE, IPR_STORE_FLOAT, IPR_STORE_FIXED,
     IprSchedule, IprResult, IprError, library_path, load,
     ipr_schedule_default, ipr_workspace_size, ipr_solve, ipr_solve_batched, ipr_gemm, ipr_lowdin,
-    ipr_solve_noalloc, IPR_NOALLOC_SCRATCH_BYTES,
+    ipr_solve_noalloc, IPR_NOALLOC_SCRATCH_BYTES, ipr_eigvalsh,
     ipr_gemm_lowp, ipr_gemm_lowp_workspace, ipr_gemm_emul, ipr_gemm_emul_workspace, ipr_norms,
     ipr_features, ipr_mlp_forward, ipr_mlp_train_step, ipr_mlp_workspace, ipr_last_error, ipr_tune_batched,
     ipr_get_batched_tiles, ipr_set_batched_tiles, IPR_BATCH_BUCKETS, ipr_spectral_counts,

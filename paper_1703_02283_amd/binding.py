@@ -107,6 +107,9 @@ _SIGS = {
                                        ct.c_void_p]),
     "ipr_solve_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_double,
                                      ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "ipr_eigvalsh": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                                ct.c_void_p]),
+    "ipr_eigvalsh_workspace": (ct.c_size_t, [ct.c_int]),
     "ipr_get_batched_tiles": (ct.c_int, [ct.c_void_p]),
     "ipr_set_batched_tiles": (ct.c_int, [ct.c_void_p]),
 }
@@ -355,6 +358,18 @@ def ipr_gemm_emul(L, R, slices=10, out=None, workspace=None, stream=None, triang
     _check(_fn("ipr_gemm_emul")(_ptr(L), _ptr(R), _ptr(D), n, int(slices), 1 if triangle else 0,
                                 _ptr(ws), ws.numel(), _stream(stream)))
     return D
+
+
+def ipr_eigvalsh(A, out=None, workspace=None, stream=None):
+    """Eigenvalues (ascending, float64 device tensor of n) of the symmetric A."""
+    _need(A, torch.float64, name="A")
+    n = A.shape[0]
+    W = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _need(W, torch.float64, (n,), "out")
+    ws = workspace if workspace is not None else _workspace(
+        int(_fn("ipr_eigvalsh_workspace")(n)), A.device)
+    _check(_fn("ipr_eigvalsh")(_ptr(A), n, _ptr(W), _ptr(ws), ws.numel(), _stream(stream)))
+    return W
 
 
 def ipr_norms(A, workspace=None, stream=None):

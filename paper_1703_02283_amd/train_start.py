@@ -1,6 +1,7 @@
 """Training and evaluation of the learned start (weights: start_mlp.npz).
 
-    python -m paper_1703_02283_amd.train_start --train 200000 --heldout 10000
+    python -m paper_1703_02283_amd.train_start --train 200000 --heldout 10000 \
+        --hh-train 40000 --hh-heldout 2000
 
 The start C_0 = s^{-1/p} q(A/s), q(x) = b0 + b1 x + b2 x^2, is expressed in
 units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4} >= lambda_max,
@@ -10,9 +11,13 @@ The network (16 -> 64 -> 64 -> 3, GELU) maps ipr_features(A) to
 
 Data: SPD matrices A = Q diag(lam) Q^T with Haar Q, n ~ U{64..1024},
 p ~ U{1..4}, kappa log-uniform in [10, 1e6] (seeds 1e6 + i for training,
-2e6 + i held out). The matrices are drawn on the GPU with torch (QR of Gaussian
-matrices, grouped by order); features, labels, training and inference all run
-in libipr's kernels:
+2e6 + i held out), plus matrices of the same draws whose eigenvectors are a
+product of 4, 16 or 64 Householder reflectors (seeds 3e6 + i and 4e6 + i):
+near-diagonal matrices, whose features the Haar set never shows and which
+large problems (the n = 16384 workload) resemble. The matrices are drawn on
+the GPU with torch (QR of Gaussian matrices or reflector updates, grouped by
+order); features, labels, training and inference all run in libipr's
+kernels:
   * labels: for every matrix, ipr_spectral_counts gives the exact-arithmetic
     iteration count of the method itself for each candidate start; the label
     is the candidate with the fewest matrix products in total (the scale
@@ -46,8 +51,12 @@ def log(*a):
     print("[train_start]", *a, file=sys.stderr, flush=True)
 
 
-def recipe(count, base_seed, n_range=(64, 1024), p_range=(1, 4), kappa_range=(10.0, 1e6)):
-    """(n, p, kappa, seed) per item; same draws as workloads.training_recipe."""
+def recipe(count, base_seed, n_range=(64, 1024), p_range=(1, 4), kappa_range=(10.0, 1e6),
+           reflectors=0):
+    """(n, p, kappa, seed, reflectors) per item; the first four are the same
+    draws as workloads.training_recipe. reflectors = 0: Haar eigenvectors;
+    otherwise the eigenvectors are a product of that many Householder
+    reflectors (4, 16 or 64, drawn per item when `reflectors` is "mix")."""
     out = []
     for i in range(count):
         s = base_seed + i
@@ -55,7 +64,8 @@ def recipe(count, base_seed, n_range=(64, 1024), p_range=(1, 4), kappa_range=(10
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         p = int(p_range[0] + int(rng.integers(0, p_range[1] - p_range[0] + 1)))
         kappa = float(np.exp(rng.uniform(np.log(kappa_range[0]), np.log(kappa_range[1]))))
-        out.append((n, p, kappa, s))
+        k = int((4, 16, 64)[int(rng.integers(0, 3))]) if reflectors == "mix" else int(reflectors)
+        out.append((n, p, kappa, s, k))
     return out
 
 
@@ -69,9 +79,15 @@ def spectrum(n, kappa, seed):
 
 
 def make_group(items, device):
-    """Matrices of one order n: Haar Q by QR of seeded Gaussians (batched on
-    the GPU), A = Q diag(lam) Q^T symmetrised. Returns (A [b, n, n], lam list)."""
+    """Matrices of one order n (and one eigenvector family): Haar Q by QR of
+    seeded Gaussians (batched on the GPU), A = Q diag(lam) Q^T symmetrised; or,
+    for items with k > 0 reflectors, A = H diag(lam) H^T with H a product of k
+    Householder reflectors of seeded Gaussian directions (diagonal plus a
+    rank-2k part: the shape of large matrices such as the n = 16384 workload).
+    Returns (A [b, n, n], lam list)."""
     n = items[0][0]
+    if items[0][4] > 0:
+        return make_group_householder(items, device)
     gen = torch.Generator(device=device)
     gen.manual_seed(items[0][3])
     g = torch.randn((len(items), n, n), dtype=torch.float64, device=device, generator=gen)
@@ -79,9 +95,28 @@ def make_group(items, device):
     d = torch.sign(torch.diagonal(r, dim1=-2, dim2=-1))
     d[d == 0] = 1.0
     q = q * d.unsqueeze(-2)
-    lams = [spectrum(n, kappa, seed) for (_, _, kappa, seed) in items]
+    lams = [spectrum(n, kappa, seed) for (_, _, kappa, seed, _) in items]
     lam_t = torch.tensor(np.stack(lams), dtype=torch.float64, device=device)
     a = (q * lam_t.unsqueeze(-2)) @ q.transpose(-1, -2).contiguous()
+    a = 0.5 * (a + a.transpose(-1, -2))
+    return a.contiguous(), lams
+
+
+def make_group_householder(items, device):
+    n, k = items[0][0], items[0][4]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(items[0][3])
+    lams = [spectrum(n, kappa, seed) for (_, _, kappa, seed, _) in items]
+    lam_t = torch.tensor(np.stack(lams), dtype=torch.float64, device=device)
+    a = torch.diag_embed(lam_t)
+    v = torch.randn((len(items), n, k), dtype=torch.float64, device=device, generator=gen)
+    v = v / torch.linalg.vector_norm(v, dim=1, keepdim=True)
+    for j in range(k):   # A <- (I - 2 v v^T) A (I - 2 v v^T)
+        x = v[:, :, j]
+        ax = torch.bmm(a, x.unsqueeze(-1)).squeeze(-1)
+        xax = (x * ax).sum(-1, keepdim=True)
+        a = (a - 2.0 * x.unsqueeze(-1) * ax.unsqueeze(-2) - 2.0 * ax.unsqueeze(-1) * x.unsqueeze(-2)
+             + 4.0 * xax.unsqueeze(-1) * x.unsqueeze(-1) * x.unsqueeze(-2))
     a = 0.5 * (a + a.transpose(-1, -2))
     return a.contiguous(), lams
 
@@ -114,7 +149,7 @@ def build_dataset(items, device, chunk=256):
     start's iteration count for every item."""
     order = {}
     for k, it in enumerate(items):
-        order.setdefault(it[0], []).append(k)
+        order.setdefault((it[0], it[4]), []).append(k)
     m = len(items)
     feats = np.zeros((m, 16), np.float32)
     labels = np.zeros((m, 3), np.float32)
@@ -134,7 +169,7 @@ def build_dataset(items, device, chunk=256):
         now = time.time()
         phase[name] += now - t
         return now
-    for n, idx in sorted(order.items()):
+    for (n, _), idx in sorted(order.items()):
         for c0 in range(0, len(idx), chunk):
             sel = idx[c0:c0 + chunk]
             its = [items[k] for k in sel]
@@ -315,6 +350,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=200000)
     ap.add_argument("--heldout", type=int, default=10000)
+    ap.add_argument("--hh-train", type=int, default=40000,
+                    help="extra training matrices with Householder-product eigenvectors")
+    ap.add_argument("--hh-heldout", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
@@ -324,30 +362,33 @@ def main():
     ipr.load()
     device = torch.device("cuda:0")
     t0 = time.time()
-    tr_items = recipe(args.train, 10**6)
-    ho_items = recipe(args.heldout, 2 * 10**6)
+    sets = {"tr": recipe(args.train, 10**6), "ho": recipe(args.heldout, 2 * 10**6),
+            "htr": recipe(args.hh_train, 3 * 10**6, reflectors="mix"),
+            "hho": recipe(args.hh_heldout, 4 * 10**6, reflectors="mix")}
+    data = {}
     if args.data and os.path.exists(args.data):
         with np.load(args.data, allow_pickle=False) as z:
-            tr = {k[3:]: z[k] for k in z.files if k.startswith("tr_")}
-            ho = {k[3:]: z[k] for k in z.files if k.startswith("ho_")}
-        assert len(tr["feats"]) == len(tr_items) and len(ho["feats"]) == len(ho_items)
+            for key in sets:
+                data[key] = {k[len(key) + 1:]: z[k] for k in z.files if k.startswith(key + "_")}
+                assert len(data[key]["feats"]) == len(sets[key])
         log(f"loaded data sets from {args.data}")
     else:
-        log("building training set")
-        tr = build_dataset(tr_items, device)
-        log("building held-out set")
-        ho = build_dataset(ho_items, device)
+        for key, items in sets.items():
+            log(f"building set {key} ({len(items)} items)")
+            data[key] = build_dataset(items, device)
         if args.data:
-            np.savez(args.data, **{"tr_" + k: v for k, v in tr.items()},
-                     **{"ho_" + k: v for k, v in ho.items()})
+            np.savez(args.data, **{f"{key}_{k}": v for key, d in data.items() for k, v in d.items()})
     t1 = time.time()
-    theta, final_loss = train(tr, device, epochs=args.epochs)
+    train_set = {k: np.concatenate([data["tr"][k], data["htr"][k]]) for k in data["tr"]}
+    theta, final_loss = train(train_set, device, epochs=args.epochs)
     t2 = time.time()
-    report = {"train_items": len(tr_items), "heldout_items": len(ho_items),
+    report = {"train_items": len(sets["tr"]), "train_items_householder": len(sets["htr"]),
+              "heldout_items": len(sets["ho"]), "heldout_items_householder": len(sets["hho"]),
               "final_loss": final_loss, "seconds_data": t1 - t0, "seconds_train": t2 - t1,
-              "train": evaluate(theta, tr_items[:min(len(tr_items), 20000)],
-                                {k: v[:20000] for k, v in tr.items()}, device),
-              "heldout": evaluate(theta, ho_items, ho, device)}
+              "train": evaluate(theta, sets["tr"][:20000],
+                                {k: v[:20000] for k, v in data["tr"].items()}, device),
+              "heldout": evaluate(theta, sets["ho"], data["ho"], device),
+              "heldout_householder": evaluate(theta, sets["hho"], data["hho"], device)}
     np.savez(args.out, theta=theta, report=json.dumps(report))
     log(json.dumps(report, indent=1))
     if args.report:

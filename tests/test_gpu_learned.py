@@ -179,7 +179,7 @@ def test_learned_start_gains_on_heldout_sample(ipr):
     ms_i = ms_l = 0.0
     fallbacks = fail_i = fail_l = 0
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    for (n, p, kappa, seed) in items:
+    for (n, p, kappa, seed, _) in items:
         a, lam = w.batch_matrix(n, kappa, seed)
         A = dev(a)
         s = ipr.ipr_schedule_default(init=ipr.IPR_INIT_LEARNED, mlp_params=theta)
