@@ -403,6 +403,12 @@ def batched_runs(ipr, torch, w, dev, tol, reps=3):
     out = {"workload": "batch_recipe(2000): n ~ U{32..512}, p in {1,2,4}, "
                        "kappa logU[10,1e5], seeds 1000+i", "tol": tol,
            "matrices": len(ns), "elements": tot}
+    # the tile-edge autotuner (per size bucket, timed on the device) sets the
+    # table the runs below use
+    t = time.perf_counter()
+    out["tuned_tiles"] = ipr.ipr_tune_batched(workspace_bytes=2 << 30)
+    out["tuning_seconds"] = time.perf_counter() - t
+    log("batched tuned tiles", out["tuned_tiles"])
     for name, kw in (("fp64_power_scale_scaled_steps",
                       dict(scale_squarings=6, dynamic_scaling=1)),
                      ("fp64", {}), ("bf16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_BF16))):

@@ -3,6 +3,9 @@
     python -m paper_1703_02283_amd.train_start --train 200000 --heldout 10000 \
         --hh-train 40000 --hh-heldout 2000
 
+or in parts: --build SET:START:STOP:FILE writes the features and labels of
+part of one set, and --shards FILE... trains and evaluates from such parts.
+
 The start C_0 = s^{-1/p} q(A/s), q(x) = b0 + b1 x + b2 x^2, is expressed in
 units of the certified bound s = (||A^2||_1 ||A^2||_inf)^{1/4} >= lambda_max,
 so the spectrum of A/s lies in (0, 1] and eq. (2) is checked on that interval.
@@ -91,10 +94,20 @@ def make_group(items, device):
     gen = torch.Generator(device=device)
     gen.manual_seed(items[0][3])
     g = torch.randn((len(items), n, n), dtype=torch.float64, device=device, generator=gen)
-    q, r = torch.linalg.qr(g)
-    d = torch.sign(torch.diagonal(r, dim1=-2, dim2=-1))
-    d[d == 0] = 1.0
-    q = q * d.unsqueeze(-2)
+    # Q of G = Q R with diag(R) > 0 (the Haar draw): Q = G R^{-1} with R^T R =
+    # G^T G (Cholesky), done twice so that Q is orthogonal to rounding
+    # (Cholesky QR; the same Q as a Householder QR with the signs fixed, which
+    # batched on the GPU is an order of magnitude slower)
+    q = g
+    for _ in range(2):
+        low = torch.linalg.cholesky(q.transpose(-1, -2) @ q)
+        # (the batched triangular solve runs out of library workspace on
+        # large batches: eight matrices per call)
+        qt = q.transpose(-1, -2).contiguous()
+        for s0 in range(0, len(items), 8):
+            qt[s0:s0 + 8] = torch.linalg.solve_triangular(low[s0:s0 + 8], qt[s0:s0 + 8],
+                                                          upper=False)
+        q = qt.transpose(-1, -2)
     lams = [spectrum(n, kappa, seed) for (_, _, kappa, seed, _) in items]
     lam_t = torch.tensor(np.stack(lams), dtype=torch.float64, device=device)
     a = (q * lam_t.unsqueeze(-2)) @ q.transpose(-1, -2).contiguous()
@@ -170,8 +183,11 @@ def build_dataset(items, device, chunk=256):
         phase[name] += now - t
         return now
     for (n, _), idx in sorted(order.items()):
-        for c0 in range(0, len(idx), chunk):
-            sel = idx[c0:c0 + chunk]
+        # (batched triangular solves of large orders run out of library
+        # workspace beyond a few hundred MB per call)
+        step = max(16, min(chunk, (1 << 25) // (n * n)))
+        for c0 in range(0, len(idx), step):
+            sel = idx[c0:c0 + step]
             its = [items[k] for k in sel]
             t = time.time()
             a, lams = make_group(its, device)
@@ -346,6 +362,12 @@ def evaluate(theta, items, data, device):
     return res
 
 
+def sets_of(args):
+    return {"tr": recipe(args.train, 10**6), "ho": recipe(args.heldout, 2 * 10**6),
+            "htr": recipe(args.hh_train, 3 * 10**6, reflectors="mix"),
+            "hho": recipe(args.hh_heldout, 4 * 10**6, reflectors="mix")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=200000)
@@ -356,28 +378,42 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
-    ap.add_argument("--data", default=None,
-                    help="npz of built data sets: loaded when it exists, else written")
+    ap.add_argument("--build", default=None, metavar="SET:START:STOP:FILE",
+                    help="only build items START..STOP-1 of set tr/ho/htr/hho into FILE (npz)")
+    ap.add_argument("--shards", nargs="*", default=None,
+                    help="npz files written by --build: train from them instead of building")
     args = ap.parse_args()
     ipr.load()
     device = torch.device("cuda:0")
     t0 = time.time()
-    sets = {"tr": recipe(args.train, 10**6), "ho": recipe(args.heldout, 2 * 10**6),
-            "htr": recipe(args.hh_train, 3 * 10**6, reflectors="mix"),
-            "hho": recipe(args.hh_heldout, 4 * 10**6, reflectors="mix")}
+    sets = sets_of(args)
+    if args.build:
+        key, a, b, path = args.build.split(":")
+        a, b = int(a), int(b)
+        log(f"building set {key} items {a}..{b - 1}")
+        d = build_dataset(sets[key][a:b], device)
+        np.savez(path, set=key, start=a, stop=b, **d)
+        log(f"wrote {path} in {time.time() - t0:.0f} s")
+        return
     data = {}
-    if args.data and os.path.exists(args.data):
-        with np.load(args.data, allow_pickle=False) as z:
-            for key in sets:
-                data[key] = {k[len(key) + 1:]: z[k] for k in z.files if k.startswith(key + "_")}
-                assert len(data[key]["feats"]) == len(sets[key])
-        log(f"loaded data sets from {args.data}")
+    if args.shards:
+        parts = {}
+        for f in args.shards:
+            with np.load(f, allow_pickle=False) as z:
+                parts.setdefault(str(z["set"]), []).append(
+                    (int(z["start"]), int(z["stop"]),
+                     {k: z[k] for k in z.files if k not in ("set", "start", "stop")}))
+        for key, lst in parts.items():
+            lst.sort(key=lambda t: t[0])
+            assert lst[0][0] == 0 and all(lst[i][1] == lst[i + 1][0] for i in range(len(lst) - 1))
+            assert lst[-1][1] == len(sets[key]), (key, lst[-1][1], len(sets[key]))
+            data[key] = {k: np.concatenate([t[2][k] for t in lst]) for k in lst[0][2]}
+        log(f"loaded {len(args.shards)} shards: " + ", ".join(f"{k} {len(v['feats'])}"
+                                                              for k, v in data.items()))
     else:
         for key, items in sets.items():
             log(f"building set {key} ({len(items)} items)")
             data[key] = build_dataset(items, device)
-        if args.data:
-            np.savez(args.data, **{f"{key}_{k}": v for key, d in data.items() for k, v in d.items()})
     t1 = time.time()
     train_set = {k: np.concatenate([data["tr"][k], data["htr"][k]]) for k in data["tr"]}
     theta, final_loss = train(train_set, device, epochs=args.epochs)
