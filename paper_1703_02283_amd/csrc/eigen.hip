@@ -5,13 +5,16 @@
 //  1. Householder tridiagonalisation, one reflector per column: with x the
 //     part of column k below the diagonal, H = I - tau v v^T maps x to
 //     beta e_1; the trailing matrix B becomes H B H = B - v w^T - w v^T with
-//     p = tau B v and w = p - (tau / 2)(p . v) v. Three launches per column:
-//     the reflector (one workgroup), p = tau B v with the partial sums of
-//     p . v (one wave per row), and the rank-2 update (tiles). The trailing
-//     matrix is kept whole (both triangles), so every read is a row read.
-//     HBM-bound: about 3 (n - k)^2 doubles per column, 8 n^3 bytes in all.
-//  2. Bisection on the Sturm count of the tridiagonal matrix (d, e), one
-//     thread per eigenvalue index, from the Gershgorin interval down to the
+//     p = tau B v and w = p - (tau / 2)(p . v) v. The trailing matrix is kept
+//     whole (both triangles), so every access is a row access. Two launches
+//     per column, the update of one column fused with the product of the
+//     next (look-ahead): the first row of the updated block, and from it the
+//     next reflector (one workgroup); then the other rows, each updated and
+//     at once multiplied by the next reflector (one wave per row). HBM-bound:
+//     one read and one write of (n - k)^2 doubles per column, 16 n^3 / 3
+//     bytes in all.
+//  2. Multisection on the Sturm count of the tridiagonal matrix (d, e), one
+//     wave per eigenvalue index, from the Gershgorin interval down to the
 //     spacing of doubles.
 #include <hip/hip_runtime.h>
 
@@ -95,46 +98,100 @@ __global__ __launch_bounds__(NT) void trail_gemv_kernel(const double* __restrict
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// B -= V W^T + W V^T with W = P - (tau / 2)(P . V) V; 64 x 64 tiles of B,
-// each workgroup sums the gemv's partials itself (fixed order).
-__global__ __launch_bounds__(NT) void trail_syr2_kernel(double* __restrict__ T, int n, int k,
-                                                        const double* __restrict__ V,
-                                                        const double* __restrict__ P,
-                                                        const double* __restrict__ tau,
-                                                        const double* __restrict__ partial,
-                                                        int nparts) {
+// Look-ahead step after column k (trailing block B of order m = n - k - 1,
+// reflector V, tau, P = tau B V with partials): row 0 of B (row k + 1 of T)
+// is updated, B_0j -= V_0 W_j + W_0 V_j with W = P - c V, c = (tau / 2) P . V,
+// and the reflector of column k + 1 is formed from it: V2, tau2, d[k + 1],
+// e[k + 1]. One workgroup; each thread reads back only the row entries it
+// wrote itself.
+__global__ __launch_bounds__(NT) void next_reflector_kernel(
+    double* __restrict__ T, int n, int k, const double* __restrict__ V,
+    const double* __restrict__ P, const double* __restrict__ tau,
+    const double* __restrict__ partial, int nparts, double* __restrict__ V2,
+    double* __restrict__ d, double* __restrict__ e, double* __restrict__ tau2) {
   __shared__ double red[NT / 64];
-  __shared__ double cs;
-  __shared__ double vi[64], wi[64], vj[64], wj[64];
+  __shared__ double head[2];  // updated B_00 and B_01
+  __shared__ double coef[2];
   const int m = n - k - 1;
   double s = 0.0;
   for (int b = threadIdx.x; b < nparts; b += NT) s += partial[b];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) cs = 0.5 * *tau * ((red[0] + red[1]) + (red[2] + red[3]));
+  const double c = 0.5 * *tau * ((red[0] + red[1]) + (red[2] + red[3]));
+  __syncthreads();  // (red is reused below)
+  const double v0 = V[0], w0 = P[0] - c * V[0];
+  double* row = T + (size_t)(k + 1) * n + k + 1;
+  double q = 0.0;  // |x|^2 beyond its first entry, x = B_0j for j = 1 .. m-1
+  for (int j = threadIdx.x; j < m; j += NT) {
+    const double t = row[j] - (v0 * (P[j] - c * V[j]) + w0 * V[j]);
+    row[j] = t;
+    if (j < 2)
+      head[j] = t;
+    else
+      q += t * t;
+  }
+  q = wave_sum(q);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
   __syncthreads();
-  const double c = cs;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  if (threadIdx.x < 64) {
-    const int i = i0 + threadIdx.x;
-    vi[threadIdx.x] = i < m ? V[i] : 0.0;
-    wi[threadIdx.x] = i < m ? P[i] - c * V[i] : 0.0;
-  } else if (threadIdx.x < 128) {
-    const int j = j0 + threadIdx.x - 64;
-    vj[threadIdx.x - 64] = j < m ? V[j] : 0.0;
-    wj[threadIdx.x - 64] = j < m ? P[j] - c * V[j] : 0.0;
+  if (threadIdx.x == 0) {
+    const double xnorm2 = (red[0] + red[1]) + (red[2] + red[3]);
+    const double alpha = head[1];
+    d[k + 1] = head[0];
+    if (xnorm2 == 0.0) {
+      e[k + 1] = alpha;
+      *tau2 = 0.0;
+      coef[0] = 0.0;
+    } else {
+      const double beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      e[k + 1] = beta;
+      *tau2 = (beta - alpha) / beta;
+      coef[0] = 1.0 / (alpha - beta);
+    }
   }
   __syncthreads();
-  const int tj = threadIdx.x & 63;
-  const int j = j0 + tj;
-  if (j >= m) return;
-  for (int r = threadIdx.x >> 6; r < 64; r += NT / 64) {
-    const int i = i0 + r;
-    if (i >= m) break;
-    double* t = T + (size_t)(k + 1 + i) * n + k + 1 + j;
-    *t -= vi[r] * wj[tj] + wi[r] * vj[tj];
+  const double cf = coef[0];
+  for (int j = threadIdx.x; j < m; j += NT)
+    if (j >= 1) V2[j - 1] = j == 1 ? 1.0 : row[j] * cf;
+}
+
+// Rows 1 .. m-1 of the trailing block B of column k, one wave per row: the
+// rank-2 update of columns 1 .. m-1 (column 0 is not read again), and in the
+// same pass P2[i - 1] = tau2 sum_j B_ij V2[j - 1], the next column's
+// product; partial2[b] = sum over the workgroup's rows of P2 V2.
+__global__ __launch_bounds__(NT) void update_gemv_kernel(
+    double* __restrict__ T, int n, int k, const double* __restrict__ V,
+    const double* __restrict__ P, const double* __restrict__ tau,
+    const double* __restrict__ partial, int nparts, const double* __restrict__ V2,
+    const double* __restrict__ tau2, double* __restrict__ P2, double* __restrict__ partial2) {
+  __shared__ double red[NT / 64];
+  const int m = n - k - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) s += partial[b];
+  s = wave_sum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  const double c = 0.5 * *tau * ((red[0] + red[1]) + (red[2] + red[3]));
+  __syncthreads();  // (red is reused below)
+  const int i = 1 + blockIdx.x * (NT / 64) + wave;
+  double pv = 0.0;
+  if (i < m) {
+    const double vi = V[i], wi = P[i] - c * V[i];
+    double* row = T + (size_t)(k + 1 + i) * n + k + 1;
+    double acc = 0.0;
+    for (int j = 1 + lane; j < m; j += 64) {
+      const double t = row[j] - (vi * (P[j] - c * V[j]) + wi * V[j]);
+      row[j] = t;
+      acc += t * V2[j - 1];
+    }
+    acc = wave_sum(acc) * *tau2;
+    if (lane == 0) P2[i - 1] = acc;
+    pv = acc * V2[i - 1];
   }
+  if (lane == 0) red[wave] = pv;
+  __syncthreads();
+  if (threadIdx.x == 0) partial2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // d[n-1] = T[n-1][n-1] (the last diagonal entry, untouched by reflectors).
@@ -143,13 +200,18 @@ __global__ void last_diag_kernel(const double* __restrict__ T, int n, double* __
 }
 
 // Eigenvalue `idx` (ascending) of the symmetric tridiagonal matrix with
-// diagonal d[0..n) and off-diagonal e[0..n-1), by bisection on the number
-// of eigenvalues below x (Sturm count of the LDL^T pivots).
-__global__ __launch_bounds__(NT) void bisect_kernel(const double* __restrict__ d,
-                                                    const double* __restrict__ e, int n,
-                                                    double* __restrict__ W) {
-  const int idx = blockIdx.x * NT + threadIdx.x;
-  if (idx >= n) return;
+// diagonal d[0..n) and off-diagonal e[0..n-1), by multisection on the
+// number of eigenvalues below x (Sturm count of the LDL^T pivots): one wave
+// per eigenvalue, its 64 lanes counting at 64 points that cut [lo, hi] into
+// 65 parts, so that every round narrows the interval 65-fold (about ten
+// rounds to the spacing of doubles, against sixty bisection steps).
+// Invariant: count(lo) <= idx < count(hi).
+__global__ __launch_bounds__(NT) void multisect_kernel(const double* __restrict__ d,
+                                                       const double* __restrict__ e, int n,
+                                                       double* __restrict__ W) {
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (idx >= n) return;  // (the whole wave: idx is uniform in it)
   double lo = d[0], hi = d[0], emax = 0.0;
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
@@ -161,9 +223,8 @@ __global__ __launch_bounds__(NT) void bisect_kernel(const double* __restrict__ d
   const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax * emax);
   lo -= 2.0 * 2.220446049250313e-16 * scale + pivmin;
   hi += 2.0 * 2.220446049250313e-16 * scale + pivmin;
-  for (int it = 0; it < 200; ++it) {
-    const double x = 0.5 * (lo + hi);
-    if (!(x > lo && x < hi)) break;  // no double strictly between: converged
+  for (int round = 0; round < 64; ++round) {
+    const double x = lo + (lane + 1) * ((hi - lo) / 65.0);
     int below = 0;
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -173,33 +234,41 @@ __global__ __launch_bounds__(NT) void bisect_kernel(const double* __restrict__ d
       if (fabs(q) < pivmin) q = -pivmin;
       below += q < 0.0;
     }
-    if (below > idx)
-      hi = x;
-    else
-      lo = x;
+    // the lanes whose point lies above eigenvalue idx form a suffix of the wave
+    const unsigned long long above = __ballot(below > idx);
+    const int j = above ? __ffsll(above) - 1 : 64;
+    const double xlo = __shfl(x, j > 0 ? j - 1 : 0, 64);
+    const double xhi = __shfl(x, j < 64 ? j : 63, 64);
+    const double nlo = j == 0 ? lo : xlo;
+    const double nhi = j == 64 ? hi : xhi;
+    if (!(nlo > lo || nhi < hi)) break;  // no double left between the points
+    lo = nlo;
+    hi = nhi;
   }
-  W[idx] = 0.5 * (lo + hi);
+  if (lane == 0) W[idx] = 0.5 * (lo + hi);
 }
 
 struct EigWork {
   double* T;
-  double* V;
-  double* P;
+  double* V[2];
+  double* P[2];
   double* d;
   double* e;
-  double* tau;
-  double* partial;
+  double* tau[2];
+  double* partial[2];
 };
 
 size_t eig_carve(int n, EigWork* w, void* base, size_t cap, bool* ok) {
   Carver c(base, cap);
   w->T = c.take<double>((size_t)n * n);
-  w->V = c.take<double>(n);
-  w->P = c.take<double>(n);
+  for (int b = 0; b < 2; ++b) {
+    w->V[b] = c.take<double>(n);
+    w->P[b] = c.take<double>(n);
+    w->tau[b] = c.take<double>(1);
+    w->partial[b] = c.take<double>((n + NT / 64 - 1) / (NT / 64) + 1);
+  }
   w->d = c.take<double>(n);
   w->e = c.take<double>(n);
-  w->tau = c.take<double>(1);
-  w->partial = c.take<double>((n + NT / 64 - 1) / (NT / 64) + 1);
   *ok = c.ok();
   return c.used;
 }
@@ -230,24 +299,34 @@ int ipr_eigvalsh(const double* dA, int n, double* dW, void* dWork, size_t work_b
                 ipr_eigvalsh_workspace(n));
   HIP_TRY(hipMemcpyAsync(w.T, dA, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice,
                          stream));
-  for (int k = 0; k + 1 < n; ++k) {
-    const int m = n - k - 1;
-    hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(NT), 0, stream, w.T, n, k, w.V, w.d, w.e,
-                       w.tau);
+  if (n >= 2) {
+    // column 0: its reflector and product; then, per column k, the update of
+    // its block fused with the next column's reflector and product
+    hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(NT), 0, stream, w.T, n, 0, w.V[0], w.d,
+                       w.e, w.tau[0]);
     HIP_TRY(hipGetLastError());
-    const int gb = (m + NT / 64 - 1) / (NT / 64);
-    hipLaunchKernelGGL(trail_gemv_kernel, dim3(gb), dim3(NT), 0, stream, w.T, n, k, w.V, w.tau,
-                       w.P, w.partial);
+    int nparts = (n - 1 + NT / 64 - 1) / (NT / 64);
+    hipLaunchKernelGGL(trail_gemv_kernel, dim3(nparts), dim3(NT), 0, stream, w.T, n, 0, w.V[0],
+                       w.tau[0], w.P[0], w.partial[0]);
     HIP_TRY(hipGetLastError());
-    const int tt = (m + 63) / 64;
-    hipLaunchKernelGGL(trail_syr2_kernel, dim3(tt, tt), dim3(NT), 0, stream, w.T, n, k, w.V,
-                       w.P, w.tau, w.partial, gb);
-    HIP_TRY(hipGetLastError());
+    for (int k = 0; k + 3 <= n; ++k) {
+      const int m = n - k - 1, a = k & 1, b = a ^ 1;
+      hipLaunchKernelGGL(next_reflector_kernel, dim3(1), dim3(NT), 0, stream,
+                         w.T, n, k, w.V[a], w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d,
+                         w.e, w.tau[b]);
+      HIP_TRY(hipGetLastError());
+      const int nb = (m - 1 + NT / 64 - 1) / (NT / 64);
+      hipLaunchKernelGGL(update_gemv_kernel, dim3(nb), dim3(NT), 0, stream, w.T, n, k, w.V[a],
+                         w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.tau[b], w.P[b],
+                         w.partial[b]);
+      HIP_TRY(hipGetLastError());
+      nparts = nb;
+    }
   }
   hipLaunchKernelGGL(last_diag_kernel, dim3(1), dim3(64), 0, stream, w.T, n, w.d);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(bisect_kernel, dim3((n + NT - 1) / NT), dim3(NT), 0, stream, w.d, w.e, n,
-                     dW);
+  hipLaunchKernelGGL(multisect_kernel, dim3((n + NT / 64 - 1) / (NT / 64)), dim3(NT), 0, stream,
+                     w.d, w.e, n, dW);
   HIP_TRY(hipGetLastError());
   return IPR_OK;
 }
