@@ -1,7 +1,7 @@
-// C ABI of the batched solver: validation, longest-processing-time
-// assignment of matrices to workgroups, the persistent launch captured in a
-// HIP graph (replayed when the same call repeats), results, and the
-// tile-edge autotuner.
+// C ABI of the batched solver: validation, the order in which workgroups
+// take the matrices (largest estimated work first), the persistent launch
+// captured in a HIP graph (replayed when the same call repeats), results,
+// and the tile-edge autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,7 +10,6 @@
 #include <limits>
 #include <mutex>
 #include <numeric>
-#include <queue>
 #include <vector>
 
 #include "../../include/ipr.h"
@@ -44,7 +43,7 @@ struct Layout {
   double* scratch;
   BatchItem* items;
   int* order;
-  int* wg_begin;
+  int* next;
   BatchResult* results;
 };
 
@@ -54,42 +53,28 @@ size_t layout(int batch, int grid, size_t scratch_elems, void* base, size_t cap,
   L->scratch = c.take<double>(scratch_elems);
   L->items = c.take<BatchItem>(batch);
   L->order = c.take<int>(batch);
-  L->wg_begin = c.take<int>(grid + 1);
+  L->next = c.take<int>(1);
   L->results = c.take<BatchResult>(batch);
   *ok = c.ok();
   return c.used;
 }
 
-// Longest processing time first: items sorted by estimated work, each given
-// to the least loaded workgroup. Output: order (grouped by workgroup) and
-// wg_begin offsets.
-void lpt(const std::vector<BatchItem>& items, int grid, std::vector<int>* order,
-         std::vector<int>* wg_begin) {
-  const int m = (int)items.size();
-  std::vector<int> idx(m);
+// Items by decreasing estimated work: n^3 times the products of one update
+// (p + 1, or log2 p + 2 by binary powering for powers of two from 4). The
+// workgroups take them in this order as they become free.
+std::vector<int> work_order(const std::vector<BatchItem>& items) {
+  std::vector<int> idx(items.size());
   std::iota(idx.begin(), idx.end(), 0);
   auto cost = [&](int i) {
     const double n = items[i].n;
-    return n * n * n * (items[i].p + 1);
+    const int p = items[i].p;
+    const bool binary = p >= 4 && (p & (p - 1)) == 0;
+    int lg = 0;
+    while ((1 << (lg + 1)) <= p) ++lg;
+    return n * n * n * (binary ? lg + 2 : p + 1);
   };
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
-  typedef std::pair<double, int> Load;
-  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-  for (int w = 0; w < grid; ++w) heap.push({0.0, w});
-  std::vector<std::vector<int>> lists(grid);
-  for (int i : idx) {
-    Load l = heap.top();
-    heap.pop();
-    lists[l.second].push_back(i);
-    heap.push({l.first + cost(i), l.second});
-  }
-  order->clear();
-  wg_begin->assign(grid + 1, 0);
-  for (int w = 0; w < grid; ++w) {
-    (*wg_begin)[w] = (int)order->size();
-    order->insert(order->end(), lists[w].begin(), lists[w].end());
-  }
-  (*wg_begin)[grid] = (int)order->size();
+  return idx;
 }
 
 // One cached executable graph of the persistent launch, keyed by its arguments.
@@ -148,13 +133,10 @@ int run_batch(const double* dA, double* dC, const std::vector<BatchItem>& items,
   bool ok;
   layout(batch, grid, scratch, dWork, work_bytes, &L, &ok);
   if (!ok) return fail(IPR_EARG, "ipr_solve_batched: workspace too small (%zu bytes)", work_bytes);
-  std::vector<int> order, wg_begin;
-  lpt(items, grid, &order, &wg_begin);
+  const std::vector<int> order = work_order(items);
   HIP_TRY(hipMemcpyAsync(L.items, items.data(), batch * sizeof(BatchItem), hipMemcpyHostToDevice,
                          stream));
   HIP_TRY(hipMemcpyAsync(L.order, order.data(), batch * sizeof(int), hipMemcpyHostToDevice, stream));
-  HIP_TRY(hipMemcpyAsync(L.wg_begin, wg_begin.data(), (grid + 1) * sizeof(int),
-                         hipMemcpyHostToDevice, stream));
   BatchArgs a;
   std::memset(&a, 0, sizeof a);
   a.A = dA;
@@ -162,7 +144,8 @@ int run_batch(const double* dA, double* dC, const std::vector<BatchItem>& items,
   a.scratch = L.scratch;
   a.items = L.items;
   a.order = L.order;
-  a.wg_begin = L.wg_begin;
+  a.count = batch;
+  a.next = L.next;
   a.results = L.results;
   a.tol = tol;
   a.bulk_switch = s.bulk_switch;

@@ -28,8 +28,9 @@ struct BatchArgs {
   double* C;
   double* scratch;
   const BatchItem* items;
-  const int* order;      // items in workgroup order
-  const int* wg_begin;   // workgroup w owns order[wg_begin[w] .. wg_begin[w+1])
+  const int* order;      // items by decreasing estimated work
+  int count;             // items in order[]
+  int* next;             // work counter: the next position of order[] to take (zeroed per launch)
   BatchResult* results;  // by item index
   double tol, bulk_switch, stall_ratio;
   int max_iter, bulk_bf16;

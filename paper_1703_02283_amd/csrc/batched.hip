@@ -6,17 +6,21 @@
 // the final check of ||I - C^p A||_F, with the iteration loop, the stopping
 // rules and the Frobenius reductions on the device. A workgroup therefore
 // never waits for another, and the launch needs no grid-wide barrier. The
-// host assigns matrices to workgroups by longest-processing-time (estimated
-// work n^3 (p + 1)); each workgroup walks its list in order and the grid has
-// drained when every list is done.
+// host sorts the matrices by estimated work (n^3 times the products per
+// update); each workgroup takes the next one from a device counter whenever
+// it is free (greedy list scheduling, largest first), so that iteration
+// counts, unknown to the host, even out; the grid has drained when the
+// counter has passed the last matrix. Each matrix is computed by one
+// workgroup with the same code whichever takes it, so results do not depend
+// on the assignment.
 //
 // Products inside a workgroup sweep the output tiles of D = L^T R one by one
 // (triangle only: every product is a polynomial in A), FP64 MFMA
-// 16x16x4 with the same operand staging as the large-matrix kernel. The tile
-// edge (32 or 64) is chosen per matrix from a size-bucket table that the
-// autotuner fills. For p = 1 a bf16 bulk phase (Newton-Schulz order, operands
-// rounded to bf16 while they are staged into LDS, fp32 accumulation) can run
-// before the FP64 refinement.
+// 16x16x4, operands staged through registers into a double-buffered LDS slab
+// of 32 k. The tile edge (32 or 64) is chosen per matrix from a size-bucket
+// table that the autotuner fills. For p = 1 a bf16 bulk phase (Newton-Schulz
+// order, operands rounded to bf16 as they are read from LDS, fp32
+// accumulation) can run before the FP64 refinement.
 #include <cstdint>
 
 #include "batched.h"
@@ -31,17 +35,49 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
-constexpr int BK = 16;
+
+// 64 KiB of LDS per workgroup stage the operands of the in-workgroup
+// products, two workgroups per CU:
+//  * FP64 products: k slabs of KD = 16 rows in a ring of 4 slots, filled by
+//    buffer loads straight into LDS three slabs ahead of the matrix cores
+//    (no staging registers, and three slabs in flight: most operand loads
+//    miss in L2, since the batch's matrices far exceed it).
+//  * bf16 products: 32-row slabs (one bf16 16x16x32 operand) staged through
+//    registers, double-buffered.
+// Rows are unpadded: each 16-lane row of an operand read is served on its own.
+constexpr int STAGE = 8192;  // doubles
+constexpr int KD = 16;       // FP64 slab rows
+constexpr int NSLOT = 4;     // FP64 ring slots
+constexpr int DEPTH = NSLOT - 1;
+constexpr int BK = 32;       // bf16 slab rows
 
 constexpr int LZ_STEPS = 12;  // Lanczos steps of the lambda_min estimate
+constexpr int LZ_COLS = 16;   // columns per lane in its matrix-vector product (n <= 1024)
+static_assert(4 * 64 * LZ_COLS <= STAGE, "the Lanczos product's partial sums fit in LDS");
 
 struct Smem {
-  double L[2][BK][64 + 16];
-  double R[2][BK][64 + 16];
+  double stage[STAGE];
   double red[NT / 64];
   double bcast[4];
   double al[LZ_STEPS], be[LZ_STEPS];
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt on the vector-memory count only: vmcnt in bits 3:0 and 15:14,
+// expcnt (6:4) = 7 and lgkmcnt (11:8) = 15 left open
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// compiler-only fence around a hardware barrier: no wait for memory operations
+__device__ __forceinline__ void wg_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
 
 __device__ __forceinline__ double block_sum(double v, Smem& sm) {
 #pragma unroll
@@ -99,27 +135,146 @@ __device__ __forceinline__ double wepi(const WEpi& e, int n, int tri, int i, int
   return mirror ? 2.0 * q * q : q * q;
 }
 
-// One output tile of edge TB = 2 WT (4 waves, 2 x 2, each WT x WT) of
-// D = L^T R, FP64 or bf16-rounded operands (LP).
-template <int WT, bool LP>
-__device__ double wg_tile(const double* __restrict__ L, const double* __restrict__ R, int n,
-                          int i0, int j0, int tri, const WEpi& e, Smem& sm) {
+// Workgroup-uniform values read from memory land in vector registers; moving
+// them to scalar registers keeps the tile loops' vector registers free.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T* uni(T* v) { return (T*)uni((uint64_t)v); }
+__device__ __forceinline__ double uni(double v) {
+  return __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, v)));
+}
+
+// FP64 output tile of edge TB = 2 WT (4 waves, 2 x 2, each WT x WT) of
+// D = L^T R. Operand slabs come in by buffer loads into LDS whose range is
+// the n x n matrix: rows k >= n (the last slab's tail) read as zero, and
+// columns past n of an edge tile read what follows in memory, which reaches
+// only outputs outside the matrix, never written. VB: bytes per lane and
+// load, 16 when every row start is 16-byte aligned, else 4.
+template <int WT, int VB>
+__device__ double wg_tile_f64(const double* __restrict__ L, const double* __restrict__ R, int n,
+                              int i0, int j0, int tri, const WEpi& e, Smem& sm) {
   constexpr int TB = 2 * WT;
-  constexpr int FB = WT / 16;  // 16 x 16 blocks per wave edge
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int FB = WT / 16;                       // 16 x 16 blocks per wave edge
+  constexpr int SLOT = 2 * KD * TB;                 // doubles per slot: L slab, then R slab
+  constexpr int IPW = KD * TB * 8 / (64 * VB) / 4;  // loads per wave, operand and slab
+  constexpr int LPS = 2 * IPW;                      // loads per wave and slab
+  static_assert(IPW >= 1 && NSLOT * SLOT <= STAGE, "slab layout");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm0 = (wave >> 1) * WT, wn0 = (wave & 1) * WT;
   const int fr = lane >> 4, fc = lane & 15;
   v4d acc[FB][FB];
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  // (the buffer descriptors must sit in scalar registers)
+  const uint32_t nbytes = (uint32_t)uni(n) * (uint32_t)uni(n) * 8u;
+  const __amdgpu_buffer_rsrc_t rl =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(uni(L)), 0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rr =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(uni(R)), 0, (int)nbytes, 0x00020000);
+  const uint32_t lds0 =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)&sm.stage[0]);
+  // load h of this wave moves bytes f = ((wave IPW + h) 64 + lane) VB of an
+  // operand's slab (row f / 8 TB, byte f % 8 TB of the row); its byte offset
+  // in the matrix, for slab 0:
+  uint32_t gl[IPW], gr[IPW];
+#pragma unroll
+  for (int h = 0; h < IPW; ++h) {
+    const uint32_t f = (uint32_t)(((wave * IPW + h) * 64 + lane) * VB);
+    const uint32_t kr = f / (8 * TB), cb = f % (8 * TB);
+    gl[h] = (kr * (uint32_t)n + (uint32_t)i0) * 8u + cb;
+    gr[h] = (kr * (uint32_t)n + (uint32_t)j0) * 8u + cb;
+  }
+  auto issue = [&](int sl) {
+    const uint32_t koff = (uint32_t)(sl * KD) * (uint32_t)n * 8u;
+    const uint32_t slot = lds0 + (uint32_t)((sl % NSLOT) * SLOT) * 8u;
+#pragma unroll
+    for (int h = 0; h < IPW; ++h) {
+      const uint32_t d = slot + (uint32_t)((wave * IPW + h) * 64 * VB);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rl, (lds_void*)(uintptr_t)d, VB, gl[h] + koff, 0,
+                                               0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rr, (lds_void*)(uintptr_t)(d + KD * TB * 8), VB,
+                                               gr[h] + koff, 0, 0, 0);
+    }
+  };
+  const int nk = (n + KD - 1) / KD;
+  wg_barrier();  // every wave is done reading the previous tile's slabs
+  for (int d = 0; d < DEPTH && d < nk; ++d) issue(d);
+  for (int sl = 0; sl < nk; ++sl) {
+    // wait for slab sl (loads complete in issue order; the slabs issued
+    // after it may stay in flight)
+    const int after = nk - 1 - sl;
+    if (after >= 2)
+      wait_vm<2 * LPS>();
+    else if (after == 1)
+      wait_vm<LPS>();
+    else
+      wait_vm<0>();
+    wg_barrier();  // slab sl is in LDS for every wave; slot (sl + DEPTH) % NSLOT is free
+    if (sl + DEPTH < nk) issue(sl + DEPTH);
+    const double* Ls = &sm.stage[(sl % NSLOT) * SLOT];
+    const double* Rs = Ls + KD * TB;
+#pragma unroll
+    for (int kk = 0; kk < KD; kk += 4) {
+      double av[FB], bv[FB];
+#pragma unroll
+      for (int a = 0; a < FB; ++a) av[a] = Ls[(kk + fr) * TB + wm0 + a * 16 + fc];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) bv[b] = Rs[(kk + fr) * TB + wn0 + b * 16 + fc];
+#pragma unroll
+      for (int a = 0; a < FB; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if constexpr (FB == 1) {
+      // With one 16 x 16 block per wave no independent instruction follows
+      // the slab's last FP64 MFMA. On gfx950 that instruction takes 16
+      // passes, so a vector read of its result needs 19 wait states; the
+      // compiler's hazard padding on the loop's exit path is shorter (9),
+      // and the last-written accumulator lanes were read stale. Pad here,
+      // with the accumulator tied so that no read is hoisted above the pad.
+      asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+v"(acc[0][0]));
+    }
+  }
+  double ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < FB; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ps += wepi(e, n, tri, i0 + wm0 + a * 16 + fr + 4 * r, j0 + wn0 + b * 16 + fc,
+                   acc[a][b][r]);
+  return ps;
+}
+
+// bf16 output tile (operands rounded to bf16 as they are read from LDS,
+// fp32 accumulation), edge TB = 2 WT, 32-row slabs staged through registers.
+template <int WT>
+__device__ double wg_tile_lp(const double* __restrict__ L, const double* __restrict__ R, int n,
+                             int i0, int j0, int tri, const WEpi& e, Smem& sm) {
+  constexpr int TB = 2 * WT;
+  constexpr int FB = WT / 16;
+  static_assert(2 * 2 * BK * TB <= STAGE, "slab layout");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * WT, wn0 = (wave & 1) * WT;
+  const int fr = lane >> 4, fc = lane & 15;
   v4f accf[FB][FB];
 #pragma unroll
   for (int a = 0; a < FB; ++a)
 #pragma unroll
-    for (int b = 0; b < FB; ++b) {
-      acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-      accf[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-    }
-  // staging: BK x TB doubles per operand, NT threads, CH elements each
-  constexpr int CH = BK * TB / NT;  // 8 (TB=128), 4 (64), 2 (32)
+    for (int b = 0; b < FB; ++b) accf[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  // buffer b: L slab at stage[2 b BK TB], R slab after it
+  constexpr int CH = BK * TB / NT;  // 8 (TB=64), 4 (32)
   double la[CH], ra[CH];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -135,9 +290,8 @@ __device__ double wg_tile(const double* __restrict__ L, const double* __restrict
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int idx = tid + q * NT;
-      const int kr = idx / TB, c = idx % TB;
-      sm.L[buf][kr][c] = la[q];
-      sm.R[buf][kr][c] = ra[q];
+      sm.stage[2 * buf * BK * TB + idx] = la[q];
+      sm.stage[(2 * buf + 1) * BK * TB + idx] = ra[q];
     }
   };
   const int nk = (n + BK - 1) / BK;
@@ -148,55 +302,24 @@ __device__ double wg_tile(const double* __restrict__ L, const double* __restrict
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * BK);
-    if constexpr (!LP) {
+    const double* Ls = &sm.stage[2 * buf * BK * TB];
+    const double* Rs = Ls + BK * TB;
+    // the bf16 16x16x32 operand spans the slab's 32 k: lane group fr
+    // supplies k = 8 fr .. 8 fr + 7
+    v8bf av[FB], bv[FB];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double av[FB], bv[FB];
+    for (int a = 0; a < FB; ++a)
 #pragma unroll
-        for (int a = 0; a < FB; ++a) av[a] = sm.L[buf][kk + fr][wm0 + a * 16 + fc];
+      for (int t = 0; t < 8; ++t) av[a][t] = (__bf16)(float)Ls[(fr * 8 + t) * TB + wm0 + a * 16 + fc];
 #pragma unroll
-        for (int b = 0; b < FB; ++b) bv[b] = sm.R[buf][kk + fr][wn0 + b * 16 + fc];
+    for (int b = 0; b < FB; ++b)
 #pragma unroll
-        for (int a = 0; a < FB; ++a)
+      for (int t = 0; t < 8; ++t) bv[b][t] = (__bf16)(float)Rs[(fr * 8 + t) * TB + wn0 + b * 16 + fc];
 #pragma unroll
-          for (int b = 0; b < FB; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-      if constexpr (FB == 1) {
-        // With one 16 x 16 block per wave no independent instruction follows
-        // the slab's last FP64 MFMA. On gfx950 that instruction takes 16
-        // passes, so a vector read of its result needs 19 wait states; the
-        // compiler's hazard padding on the loop's exit path is shorter (9),
-        // and the last-written accumulator lanes were read stale. Pad here,
-        // with the accumulator tied so that no read is hoisted above the pad.
-        asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 4" : "+a"(acc[0][0]));
-      }
-    } else {
-      // The bf16 16x16x32 operand spans 32 k and a slab holds 16: lanes whose
-      // k is 16..31 supply zeros (half of the instruction's k width idles).
-      v8bf av[FB], bv[FB];
+    for (int a = 0; a < FB; ++a)
 #pragma unroll
-      for (int a = 0; a < FB; ++a) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = fr * 8 + t;  // 0..31; k >= 16 are zero
-          av[a][t] = k < BK ? (__bf16)(float)sm.L[buf][k][wm0 + a * 16 + fc] : (__bf16)0.0f;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < FB; ++b) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = fr * 8 + t;
-          bv[b][t] = k < BK ? (__bf16)(float)sm.R[buf][k][wn0 + b * 16 + fc] : (__bf16)0.0f;
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < FB; ++a)
-#pragma unroll
-        for (int b = 0; b < FB; ++b)
-          accf[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], accf[a][b], 0, 0, 0);
-    }
+      for (int b = 0; b < FB; ++b)
+        accf[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], accf[a][b], 0, 0, 0);
     if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
@@ -206,14 +329,9 @@ __device__ double wg_tile(const double* __restrict__ L, const double* __restrict
 #pragma unroll
     for (int b = 0; b < FB; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if constexpr (!LP)
-          ps += wepi(e, n, tri, i0 + wm0 + a * 16 + fr + 4 * r, j0 + wn0 + b * 16 + fc,
-                     acc[a][b][r]);
-        else
-          ps += wepi(e, n, tri, i0 + wm0 + a * 16 + 4 * fr + r, j0 + wn0 + b * 16 + fc,
-                     (double)accf[a][b][r]);
-      }
+      for (int r = 0; r < 4; ++r)
+        ps += wepi(e, n, tri, i0 + wm0 + a * 16 + 4 * fr + r, j0 + wn0 + b * 16 + fc,
+                   (double)accf[a][b][r]);
   return ps;
 }
 
@@ -224,13 +342,20 @@ template <bool LP>
 __device__ double wg_product(const double* L, const double* R, int n, int tri, int tile,
                              const WEpi& e, Smem& sm) {
   const int nt = (n + tile - 1) / tile;
+  const bool v16 = !(n & 1) && !(((uintptr_t)L | (uintptr_t)R) & 15);
   double ps = 0.0;
   for (int bi = 0; bi < nt; ++bi)
     for (int bj = tri ? bi : 0; bj < nt; ++bj) {
-      if (tile == 64)
-        ps += wg_tile<32, LP>(L, R, n, bi * 64, bj * 64, tri, e, sm);
+      const int i0 = bi * tile, j0 = bj * tile;
+      if constexpr (LP)
+        ps += tile == 64 ? wg_tile_lp<32>(L, R, n, i0, j0, tri, e, sm)
+                         : wg_tile_lp<16>(L, R, n, i0, j0, tri, e, sm);
+      else if (tile == 64)
+        ps += v16 ? wg_tile_f64<32, 16>(L, R, n, i0, j0, tri, e, sm)
+                  : wg_tile_f64<32, 4>(L, R, n, i0, j0, tri, e, sm);
       else
-        ps += wg_tile<16, LP>(L, R, n, bi * 32, bj * 32, tri, e, sm);
+        ps += v16 ? wg_tile_f64<16, 16>(L, R, n, i0, j0, tri, e, sm)
+                  : wg_tile_f64<16, 4>(L, R, n, i0, j0, tri, e, sm);
     }
   __syncthreads();  // the product is complete and visible to the workgroup
   return block_sum(ps, sm);
@@ -245,20 +370,6 @@ struct ProdDesc {
   WEpi e;
 };
 constexpr int QMAX = 12;
-
-// Workgroup-uniform values read from memory land in vector registers; moving
-// them to scalar registers keeps the tile loops' vector registers free.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ uint64_t uni(uint64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-template <class T>
-__device__ __forceinline__ T* uni(T* v) { return (T*)uni((uint64_t)v); }
-__device__ __forceinline__ double uni(double v) {
-  return __builtin_bit_cast(double, uni(__builtin_bit_cast(uint64_t, v)));
-}
 
 // Runs q[0..count) in order; returns the block-summed partial of the last.
 __device__ double run_products(const ProdDesc* q, int count, int n, int tile,
@@ -319,12 +430,34 @@ __device__ __noinline__ double lanczos_min_wg(const double* S, int n, double* ve
   int m = 0;
   for (int j = 0; j < LZ_STEPS; ++j) {
     __syncthreads();
-    for (int i = tid >> 6; i < n; i += NT / 64) {  // w = S q_j, one wave per row
-      double rs = 0.0;
-      for (int c2 = tid & 63; c2 < n; c2 += 64) rs += S[(size_t)i * n + c2] * qc[c2];
+    {
+      // w = S q_j. S is symmetric, so w is the sum over rows i of q_i times
+      // row i: wave wv takes rows wv, wv + 4, ..., each lane 16 columns of
+      // them (coalesced row segments whose loads do not wait on one another,
+      // so that many are in flight), and the four waves' partial sums meet
+      // in LDS.
+      const int lane = tid & 63, wave = tid >> 6;
+      double acc[LZ_COLS];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) rs += __shfl_xor(rs, off, 64);
-      if ((tid & 63) == 0) wv[i] = rs;
+      for (int c = 0; c < LZ_COLS; ++c) acc[c] = 0.0;
+#pragma unroll 2
+      for (int i = wave; i < n; i += NT / 64) {
+        const double qi = qc[i];
+        const double* row = S + (size_t)i * n;
+#pragma unroll
+        for (int c = 0; c < LZ_COLS; ++c) {
+          const int j = lane + 64 * c;
+          if (j < n) acc[c] += qi * row[j];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < LZ_COLS; ++c) {
+        const int j = lane + 64 * c;
+        if (j < n) sm.stage[wave * n + j] = acc[c];
+      }
+      __syncthreads();
+      for (int t = tid; t < n; t += NT)
+        wv[t] = (sm.stage[t] + sm.stage[n + t]) + (sm.stage[2 * n + t] + sm.stage[3 * n + t]);
     }
     __syncthreads();
     double pa = 0.0;
@@ -368,9 +501,14 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
   __shared__ __attribute__((aligned(16))) char qraw[QMAX * sizeof(ProdDesc)];
   ProdDesc* q = reinterpret_cast<ProdDesc*>(qraw);
   const int tid = threadIdx.x;
-  const int w = blockIdx.x;
   // each item's n (1..1024), p (1..8) and tile were checked on the host
-  for (int li = args.wg_begin[w]; li < args.wg_begin[w + 1]; ++li) {
+  __shared__ int taken;
+  for (;;) {
+    if (tid == 0) taken = atomicAdd(args.next, 1);
+    __syncthreads();
+    const int li = uni(taken);
+    __syncthreads();  // every thread has read it before it is overwritten
+    if (li >= args.count) break;
     const BatchItem it = args.items[uni(args.order[li])];
     const int n = uni(it.n), p = uni(it.p), tile = uni(it.tile);
     const size_t nn = (size_t)n * n;
@@ -790,6 +928,10 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
   }
 }
 
+__global__ void zero_counter_kernel(int* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
 __global__ __launch_bounds__(NT) void fill_test_kernel(double* A, const BatchItem* items) {
   const BatchItem it = items[blockIdx.x];
   const int n = it.n;
@@ -809,9 +951,11 @@ hipError_t batched_fill_test(double* A, const BatchItem* items, int count, hipSt
 }
 
 hipError_t batched_launch(const BatchArgs& args, int grid, hipStream_t stream) {
-  if (!args.A || !args.C || !args.scratch || !args.items || !args.order || !args.wg_begin ||
-      !args.results)
+  if (!args.A || !args.C || !args.scratch || !args.items || !args.order || !args.next ||
+      !args.results || args.count < 0)
     return hipErrorInvalidValue;
+  // the counter is cleared by a kernel (a graph may hold this launch)
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, stream, args.next);
   hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(NT), 0, stream, args);
   return hipGetLastError();
 }
