@@ -128,7 +128,8 @@ int run_batch(const double* dA, double* dC, const std::vector<BatchItem>& items,
   const int batch = (int)items.size();
   const int grid = grid_size(batch);
   size_t scratch = 0;
-  for (const auto& it : items) scratch = std::max<size_t>(scratch, it.s_off + 7 * (size_t)it.n * it.n);
+  for (const auto& it : items)
+    scratch = std::max<size_t>(scratch, it.s_off + 7 * batch_scratch_stride(it.n));
   Layout L;
   bool ok;
   layout(batch, grid, scratch, dWork, work_bytes, &L, &ok);
@@ -221,7 +222,7 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
     items[i].p = p[i];
     items[i].tile = s.tile ? s.tile : tiles[bucket_of(n[i])];
     items[i].pad = 0;
-    soff += 7 * (int64_t)n[i] * n[i];
+    soff += 7 * (int64_t)batch_scratch_stride(n[i]);
   }
   std::vector<BatchResult> res;
   if (int rc = run_batch(dA, dC, items, tol, s, dWork, work_bytes, &res, stream, true)) return rc;
@@ -282,7 +283,7 @@ int ipr_tune_batched(void* dWork, size_t work_bytes, int* tiles_out, hipStream_t
     std::vector<BatchItem> items(count);
     for (int i = 0; i < count; ++i) {
       items[i].a_off = (int64_t)i * nn;
-      items[i].s_off = (int64_t)i * 7 * nn;
+      items[i].s_off = (int64_t)i * 7 * (int64_t)batch_scratch_stride(nb);
       items[i].n = nb;
       items[i].p = 2;
       items[i].tile = table[b];
@@ -323,7 +324,9 @@ int ipr_tune_batched(void* dWork, size_t work_bytes, int* tiles_out, hipStream_t
 size_t ipr::batched_workspace_bytes(int n_max, int batch) {
   Layout L;
   bool ok;
-  return layout(batch, grid_size(batch), 7 * (size_t)n_max * n_max, nullptr, (size_t)-1, &L, &ok) +
+  // (each item's scratch stride rounds n^2 up by at most 31 elements)
+  return layout(batch, grid_size(batch), 7 * ((size_t)n_max * n_max + 32 * (size_t)batch), nullptr,
+                (size_t)-1, &L, &ok) +
          256;
 }
 

@@ -9,9 +9,16 @@ namespace ipr {
 // Resident workgroups per CU (the kernel's launch bound and the grid size).
 constexpr int kBatchWgPerCu = 2;
 
+// Elements between an item's scratch matrices: n^2 rounded up to 32, so
+// that with a 256-byte aligned scratch base every scratch matrix starts on a
+// 256-byte boundary (the products' 16-byte direct loads need 16).
+__host__ __device__ inline size_t batch_scratch_stride(int n) {
+  return ((size_t)n * n + 31) & ~(size_t)31;
+}
+
 struct BatchItem {
   int64_t a_off;   // element offset of A_i (and C_i) in the packed buffers
-  int64_t s_off;   // element offset of its 7 n_i^2 scratch matrices
+  int64_t s_off;   // element offset of its 7 scratch matrices (batch_scratch_stride apart)
   int n, p, tile, pad;
 };
 

@@ -16,11 +16,11 @@
 //
 // Products inside a workgroup sweep the output tiles of D = L^T R one by one
 // (triangle only: every product is a polynomial in A), FP64 MFMA
-// 16x16x4, operands staged through registers into a double-buffered LDS slab
-// of 32 k. The tile edge (32 or 64) is chosen per matrix from a size-bucket
-// table that the autotuner fills. For p = 1 a bf16 bulk phase (Newton-Schulz
-// order, operands rounded to bf16 as they are read from LDS, fp32
-// accumulation) can run before the FP64 refinement.
+// 16x16x4, operand slabs loaded straight into LDS. The tile edge (32 or 64)
+// is chosen per matrix from a size-bucket table that the autotuner fills.
+// For p = 1 a bf16 bulk phase (Newton-Schulz order, operands rounded to bf16
+// as they are read from LDS, fp32 accumulation) can run before the FP64
+// refinement.
 #include <cstdint>
 
 #include "batched.h"
@@ -38,7 +38,7 @@ constexpr int NT = 256;
 
 // 64 KiB of LDS per workgroup stage the operands of the in-workgroup
 // products, two workgroups per CU:
-//  * FP64 products: k slabs of KD = 16 rows in a ring of 4 slots, filled by
+//  * FP64 products: k slabs of 16 rows in a ring of 4 slots, filled by
 //    buffer loads straight into LDS three slabs ahead of the matrix cores
 //    (no staging registers, and three slabs in flight: most operand loads
 //    miss in L2, since the batch's matrices far exceed it).
@@ -222,18 +222,36 @@ __device__ double wg_tile_f64(const double* __restrict__ L, const double* __rest
     if (sl + DEPTH < nk) issue(sl + DEPTH);
     const double* Ls = &sm.stage[(sl % NSLOT) * SLOT];
     const double* Rs = Ls + KD * TB;
+    // the operands of k-step kk + 4 are read from LDS while the matrix cores
+    // work on k-step kk (LDS reads placed between the MFMAs), so that the
+    // LDS latency is not exposed at every k-step
+    double av[2][FB], bv[2][FB];
+    auto fload = [&](int kk, double* a_, double* b_) {
+#pragma unroll
+      for (int a = 0; a < FB; ++a) a_[a] = Ls[(kk + fr) * TB + wm0 + a * 16 + fc];
+#pragma unroll
+      for (int b = 0; b < FB; ++b) b_[b] = Rs[(kk + fr) * TB + wn0 + b * 16 + fc];
+    };
+    fload(0, av[0], bv[0]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kk = 0; kk < KD; kk += 4) {
-      double av[FB], bv[FB];
-#pragma unroll
-      for (int a = 0; a < FB; ++a) av[a] = Ls[(kk + fr) * TB + wm0 + a * 16 + fc];
-#pragma unroll
-      for (int b = 0; b < FB; ++b) bv[b] = Rs[(kk + fr) * TB + wn0 + b * 16 + fc];
+      const int cur = (kk >> 2) & 1;
+      if (kk + 4 < KD) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
 #pragma unroll
       for (int a = 0; a < FB; ++a)
 #pragma unroll
         for (int b = 0; b < FB; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          acc[a][b] =
+              __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b], acc[a][b], 0, 0, 0);
+      if (kk + 4 < KD) {
+#pragma unroll
+        for (int g = 0; g < FB * FB; ++g) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // 1 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 LDS read
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (FB == 1) {
       // With one 16 x 16 block per wave no independent instruction follows
@@ -336,8 +354,7 @@ __device__ double wg_tile_lp(const double* __restrict__ L, const double* __restr
 }
 
 // Whole product D = L^T R inside the workgroup; returns the block-summed
-// partial (every thread). tile: 32 or 64 (a 128 edge would need more
-// registers than a persistent kernel can hold beside its control state).
+// partial (every thread). tile: 32 or 64.
 template <bool LP>
 __device__ double wg_product(const double* L, const double* R, int n, int tri, int tile,
                              const WEpi& e, Smem& sm) {
@@ -516,14 +533,15 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     b.A = uni(args.A + it.a_off);
     double* dC = uni(args.C + it.a_off);  // C_i sits where A_i sits in its buffer
     double* s = uni(args.scratch + it.s_off);
+    const size_t sst = batch_scratch_stride(n);  // (256-byte aligned matrices)
     b.C[0] = dC;
     b.C[1] = s;
-    b.M[0] = s + nn;
-    b.M[1] = s + 2 * nn;
-    b.N[0] = s + 3 * nn;
-    b.N[1] = s + 4 * nn;
-    b.X[0] = s + 5 * nn;
-    b.X[1] = s + 6 * nn;
+    b.M[0] = s + sst;
+    b.M[1] = s + 2 * sst;
+    b.N[0] = s + 3 * sst;
+    b.N[1] = s + 4 * sst;
+    b.X[0] = s + 5 * sst;
+    b.X[1] = s + 6 * sst;
     BatchResult res;
     res.status = 2;  // EMAXITER unless set below
     res.iters_bulk = res.iters_fp64 = 0;
