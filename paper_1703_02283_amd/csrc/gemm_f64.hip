@@ -59,7 +59,7 @@ constexpr int RPW = BKD / 8;               // k rows per wave and operand per sl
 constexpr int LPS = 2 * RPW;               // direct loads per lane per slab
 constexpr int FLUSHD = 64 / BKD;           // slabs per 64-k slab accumulator
 static_assert(NSLOT * BKD == 2 * BK, "the two paths share the LDS buffers");
-static_assert(DEPTH == 3 && FLUSHD == 4, "the interior loop is written for these");
+static_assert(DEPTH == 3 && FLUSHD == 4 && NSLOT == FLUSHD, "the interior loop is written for these");
 
 // s_waitcnt with only the vector-memory count waited on: vmcnt in bits 3:0
 // and 15:14, expcnt (6:4) = 7 and lgkmcnt (11:8) = 15 left open
@@ -173,36 +173,54 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
       }
     };
     const int nk = (kSplit ? ta.klen : n) / BKD;  // a multiple of FLUSHD
+    // wait for slab sl: the slabs issued after it may stay in flight
+    auto wait_slab = [&](int sl) {
+      const int after = nk - 1 - sl;
+      if (after >= 2) wait_vm<2 * LPS>();
+      else if (after == 1) wait_vm<LPS>();
+      else wait_vm<0>();
+    };
+    auto fload = [&](int slot, int kk, double* a_, double* b_) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a) a_[a] = Lr[slot][kk + fr][wm0 + a * 16 + fc];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) b_[b] = Rr[slot][kk + fr][wn0 + b * 16 + fc];
+    };
+    double av[2][FM], bv[2][FN];
     for (int d = 0; d < DEPTH && d < nk; ++d) issue(d);
+    wait_slab(0);
+    wg_barrier();
+    if (DEPTH < nk) issue(DEPTH);
+    fload(0, 0, av[0], bv[0]);
     // The slab loop is unrolled by the 64-k chain length so that the first
     // k-step of every chain is its own code: there each block's finished
     // chain is added to the running sums and its first product starts from
-    // zero (no separate pass that clears the accumulators).
+    // zero (no separate pass that clears the accumulators). The barrier of
+    // slab sl + 1 sits before the last k-step of slab sl: by then every wave
+    // holds that step's operands, so the slot can be refilled, and the next
+    // slab's first operands are read from LDS while the matrix cores work on
+    // the last step (no LDS latency exposed at the slab boundary).
     for (int sg = 0; sg < nk; sg += FLUSHD) {
 #pragma unroll
       for (int s4 = 0; s4 < FLUSHD; ++s4) {
         const int sl = sg + s4;
-        // wait for slab sl: the slabs issued after it may stay in flight
-        const int after = nk - 1 - sl;
-        if (after >= 2) wait_vm<2 * LPS>();
-        else if (after == 1) wait_vm<LPS>();
-        else wait_vm<0>();
-        wg_barrier();  // slab sl is in LDS for every wave; slot (sl + DEPTH) % NSLOT is free
-        if (sl + DEPTH < nk) issue(sl + DEPTH);
-        const int slot = sl % NSLOT;
-        double av[2][FM], bv[2][FN];
-        auto fload = [&](int kk, double* a_, double* b_) {
-#pragma unroll
-          for (int a = 0; a < FM; ++a) a_[a] = Lr[slot][kk + fr][wm0 + a * 16 + fc];
-#pragma unroll
-          for (int b = 0; b < FN; ++b) b_[b] = Rr[slot][kk + fr][wn0 + b * 16 + fc];
-        };
-        fload(0, av[0], bv[0]);
+        const int slot = s4;  // (sg is a multiple of NSLOT)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kk = 0; kk < BKD; kk += 4) {
           const int cur = (kk >> 2) & 1;
-          if (kk + 4 < BKD) fload(kk + 4, av[cur ^ 1], bv[cur ^ 1]);
+          if (kk + 4 < BKD) {
+            fload(slot, kk + 4, av[cur ^ 1], bv[cur ^ 1]);
+          } else {
+            // (after the last slab the same steps run on no data: the wait
+            // is for every load, and the operands read are not used)
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this step's operands are in
+            wait_slab(sl + 1);
+            wg_barrier();  // slab sl + 1 is in LDS for every wave; this slot is free
+            if (sl + 1 + DEPTH < nk) issue(sl + 1 + DEPTH);
+            __builtin_amdgcn_sched_barrier(0);
+            fload((s4 + 1) % NSLOT, 0, av[cur ^ 1], bv[cur ^ 1]);
+          }
           if (s4 == 0 && kk == 0) {
 #pragma unroll
             for (int a = 0; a < FM; ++a)
@@ -230,7 +248,7 @@ void gemm_f64_kernel(const double* __restrict__ L, const double* __restrict__ R,
               for (int b = 0; b < FN; ++b)
                 slab[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[cur][a], bv[cur][b],
                                                                   slab[a][b], 0, 0, 0);
-            if (kk + 4 < BKD) {
+            {
 #pragma unroll
               for (int g = 0; g < 3; ++g) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
