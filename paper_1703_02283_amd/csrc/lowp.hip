@@ -479,14 +479,121 @@ __global__ __launch_bounds__(NT, 1) void gemm_lp_kernel(const uint8_t* __restric
 
   // a multiple of 4 (np is a multiple of 256)
   const int nst = (int)(ldb / KB) * (DT == LP_I8 ? sa.npairs : 1);
+  auto wait_stage = [&](int st) {
+    const int after = nst - 1 - st;   // stages issued after st (at most 2)
+    if (after >= 2) __builtin_amdgcn_s_waitcnt(0x4F70);       // vmcnt(16)
+    else if (after == 1) __builtin_amdgcn_s_waitcnt(0x0F78);  // vmcnt(8)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                  // vmcnt(0)
+  };
   issue(Ic<0>{}, 0);
   issue(Ic<1>{}, 1);
   issue(Ic<2>{}, 2);
-  for (int st = 0; st < nst; st += 4) {
-    stage(Ic<0>{}, st, nst);
-    stage(Ic<1>{}, st + 1, nst);
-    stage(Ic<2>{}, st + 2, nst);
-    stage(Ic<3>{}, st + 3, nst);
+  if constexpr (ESZ == 2 || DT == LP_I8) {
+    // Two k-steps per stage. The barrier of stage st + 1 sits before the
+    // last k-step of stage st: by then each wave holds that step's
+    // fragments (it waits for its LDS reads first), so the slot can be
+    // refilled right after the barrier, and the first fragments of stage
+    // st + 1 are read from LDS between the last step's MFMAs (no LDS latency
+    // exposed at the stage boundary).
+    static_assert(KB / 32 == 2, "two k-steps per stage");
+    auto frag = [&](auto S, int ks, uint4* av, uint4* bv) {
+      constexpr int sl = decltype(S)::value;
+      const uint8_t* as = sl == 0 ? A0 : sl == 1 ? A1 : sl == 2 ? A2 : A3;
+      const uint8_t* bs = sl == 0 ? B0 : sl == 1 ? B1 : sl == 2 ? B2 : B3;
+      const int c = 2 * ks + fhalf;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int row = wm * 128 + a * 32 + frow;
+        av[a] = *reinterpret_cast<const uint4*>(as + row * KB + 16 * swz(row, c));
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = wn * 128 + b * 32 + frow;
+        bv[b] = *reinterpret_cast<const uint4*>(bs + row * KB + 16 * swz(row, c));
+      }
+    };
+    auto mfmas = [&](const uint4* av, const uint4* bv) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if constexpr (DT == LP_BF16)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(v8bf, av[a]), __builtin_bit_cast(v8bf, bv[b]), acc[a][b], 0, 0,
+                0);
+          else if constexpr (DT == LP_I8)
+            // int32 results kept in the float accumulators' registers as bits
+            acc[a][b] = __builtin_bit_cast(
+                v16f, __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                          __builtin_bit_cast(v4i, av[a]), __builtin_bit_cast(v4i, bv[b]),
+                          __builtin_bit_cast(v16i, acc[a][b]), 0, 0, 0));
+          else
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(v8h, av[a]), __builtin_bit_cast(v8h, bv[b]), acc[a][b], 0, 0,
+                0);
+        }
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // 2 MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // 1 DS read
+      }
+    };
+    // fp16: stage st's fragments of A rescaled to the accumulator's units
+    auto rescale = [&](int st, uint4* av) {
+      if constexpr (DT == LP_FP16) {
+        const int kt = st / ST_PER_KT;
+        const int el = EL[ib * ntp + kt], er = ER[jb * ntp + kt];
+        // (a zero tile's codes are zero: any scale will do)
+        const int d = (el == kZeroTile || er == kZeroTile) ? 0 : el + er - sref;
+        if (d != 0) {
+          const _Float16 fsc = (_Float16)ldexpf(1.0f, d < -30 ? -30 : d);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            v8h h = __builtin_bit_cast(v8h, av[a]);
+            h = h * fsc;
+            av[a] = __builtin_bit_cast(uint4, h);
+          }
+        }
+      }
+    };
+    uint4 av[2][4], bv[2][4];
+    auto step = [&](auto S, int st) {
+      constexpr int sl = decltype(S)::value;
+      // k-step 0 of stage st (fragments in av[0]); k-step 1's are read meanwhile
+      frag(S, 1, av[1], bv[1]);
+      rescale(st, av[0]);
+      mfmas(av[0], bv[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      // k-step 1; the barrier of stage st + 1 first (after the last stage the
+      // same steps run on no data: the wait is for every load, and the
+      // fragments read are not used)
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): k-step 1's fragments are in
+      wait_stage(st + 1);
+      wg_barrier();  // stage st + 1 is in LDS for every wave; this slot is free
+      if (st + 4 < nst) issue(S, st + 4);
+      __builtin_amdgcn_sched_barrier(0);
+      frag(Ic<(sl + 1) % 4>{}, 0, av[0], bv[0]);
+      rescale(st, av[1]);
+      mfmas(av[1], bv[1]);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    wait_stage(0);
+    wg_barrier();
+    issue(Ic<3>{}, 3);
+    frag(Ic<0>{}, 0, av[0], bv[0]);
+    for (int st = 0; st < nst; st += 4) {
+      step(Ic<0>{}, st);
+      step(Ic<1>{}, st + 1);
+      step(Ic<2>{}, st + 2);
+      step(Ic<3>{}, st + 3);
+    }
+  } else {
+    for (int st = 0; st < nst; st += 4) {
+      stage(Ic<0>{}, st, nst);
+      stage(Ic<1>{}, st + 1, nst);
+      stage(Ic<2>{}, st + 2, nst);
+      stage(Ic<3>{}, st + 3, nst);
+    }
   }
 
   // Epilogue through LDS, one 32-row block of each wave at a time: the waves
