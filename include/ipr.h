@@ -259,7 +259,7 @@ int ipr_solve_batched(const double* dA_packed, double* dC_packed, const int64_t*
                       hipStream_t stream);
 
 /* Size buckets of the batched solver's tile table: bucket b holds the orders
- * n <= IPR_BATCH_BUCKET_MAX(b) (48, 96, 192, 384, 768, 1024). */
+ * up to its maximum (48, 96, 192, 384, 768, 1024) above the previous one's. */
 #define IPR_BATCH_BUCKETS 6
 
 /* Times every tile edge (32, 64) on synthetic batches of each bucket's
