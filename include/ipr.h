@@ -41,7 +41,8 @@ typedef enum {
   IPR_OK = 0,
   IPR_EARG = 1,        /* invalid argument or workspace too small */
   IPR_EMAXITER = 2,    /* max_iter updates applied without reaching tol */
-  IPR_EFLOOR = 3,      /* the residual stopped falling above tol (precision floor) */
+  IPR_EFLOOR = 3,      /* the residual stopped falling above tol (precision floor): below 1/2,
+                          where every exact step at least halves it */
   IPR_EDIVERGED = 4,   /* NaN/Inf or residual > 1e6, again after one restart from the
                           scaled identity (ipr_solve; not for the LITERAL order or
                           approximate storage, which report the first divergence) */
@@ -107,7 +108,9 @@ typedef struct {
   int guard_fallback;  /* 1: a POLY/LEARNED/PAPER_EQ3 start that fails the eq. (2) check falls back to IDENTITY (default 1) */
   int verify;          /* 1: confirm ||I - C^p A||_F < tol from C and A before returning OK (default 1) */
   double bulk_switch;  /* low-precision bulk phase ends when its residual falls below this or stalls (default 0.05) */
-  double stall_ratio;  /* "stalled" = residual not below stall_ratio * best for 2 iterations (default 0.5) */
+  double stall_ratio;  /* the low-precision bulk phase stalls when its residual is not below
+                          stall_ratio * best for 2 iterations; the FP64 phase ends on IPR_EFLOOR
+                          when, below 1/2, it is not below stall_ratio * best for 3 (default 0.5) */
   double poly[3];      /* b0, b1, b2 for IPR_INIT_POLY */
   const float* mlp_params; /* device, IPR_MLP_NPARAM floats, for IPR_INIT_LEARNED */
   int timing;          /* 1: time every matrix product with device events (ms_gemm, gemm_flops) */

@@ -30,6 +30,19 @@ import numpy as np
 
 OK, EMAXITER, EFLOOR, EDIVERGED = 0, 2, 3, 4
 
+# Residual below which a step that fails to halve it can only be rounding
+# (see ``solve``)
+FLOOR_ZONE = 0.5
+
+
+def step_contraction(p: int, emax: float = 0.5, samples: int = 200001) -> float:
+    """max |1 - g(1 - e)| / |e| over 0 < |e| <= emax, g the coupled form's
+    eigenvalue map m -> m ((p + 1 - m) / p)^p (a dense sample of e)."""
+    e = np.linspace(-emax, emax, samples)
+    e = e[e != 0.0]
+    m = 1.0 - e
+    return float(np.max(np.abs(1.0 - m * ((p + 1 - m) / p) ** p) / np.abs(e)))
+
 
 def norm_1(a: np.ndarray) -> float:
     """||A||_1: the largest column sum of absolute values (eq. (3))."""
@@ -218,8 +231,12 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
 
     The returned iteration count is the number of updates applied. Status:
     OK; EMAXITER after max_iter updates; EDIVERGED on a NaN or a residual above
-    1e6; EFLOOR when, once below 1, the residual has not fallen below half its
-    best value for ``floor_window`` consecutive iterations.
+    1e6; EFLOOR when, once below 1/2, the residual has not fallen below half
+    its best value for ``floor_window`` consecutive iterations. Below 1/2 every
+    eigenvalue error e of M_k has |e| <= 1/2, and one exact step maps it to at
+    most |e|/2 (``step_contraction``), so only rounding can keep the residual
+    from halving; between 1/2 and 1 a single small eigenvalue still in its slow
+    phase can hold the residual nearly flat for many steps.
     """
     if not np.array_equal(a, a.T):
         raise ValueError("A must be exactly symmetric")
@@ -261,7 +278,7 @@ def solve(a: np.ndarray, p: int, tol: float, init="identity", max_iter: int = 10
             tau = true_residual(c, a, p)
             if tau < tol:
                 return Result(c, OK, k, rhos, tau)
-        if rho < 1.0:
+        if rho < FLOOR_ZONE:
             if rho < 0.5 * best:
                 best = rho
                 stale = 0

@@ -821,7 +821,7 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
         }
         last_tau = tau;
       }
-      if (rho < 1.0) {
+      if (rho < kFloorZone) {
         if (rho < args.stall_ratio * best) {
           best = rho;
           stale = 0;

@@ -49,6 +49,14 @@ __host__ __device__ inline double round_store(double v, int fmt, int bits) {
   return v;
 }
 
+// Residual below which the FP64 phase counts stagnation toward IPR_EFLOOR.
+// When ||I - M_k|| <= 1/2 every eigenvalue error e of M_k has |e| <= 1/2 and
+// one exact step of eq. (1) leaves at most |e|/2 (p = 1 exactly; less for
+// p >= 2), so a step that does not halve the residual there is rounding.
+// Between 1/2 and 1 one small eigenvalue still in the slow phase of the
+// iteration can hold the residual nearly flat for several steps.
+constexpr double kFloorZone = 0.5;
+
 // Number of per-tile partial slots a product of order n writes.
 int gemm_partial_slots(int n, int tri);
 

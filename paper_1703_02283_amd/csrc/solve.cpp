@@ -671,7 +671,7 @@ int solve_arith(Solver& sv, const ipr_schedule& s, double tol, double sigma, ipr
       status = IPR_OK;
       break;
     }
-    if (rho < 1.0) {
+    if (rho < kFloorZone) {
       if (rho < s.stall_ratio * best) {
         best = rho;
         stale = 0;
@@ -1172,7 +1172,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
         status = IPR_OK;
         break;
       }
-      if (rho < 1.0) {
+      if (rho < kFloorZone) {
         if (rho < s.stall_ratio * best) {
           best = rho;
           stale = 0;
@@ -1273,7 +1273,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       floor = ++failed_verify >= 2 && !(tau < 0.5 * last_tau);
       last_tau = tau;
     }
-    if (!bad && rho < 1.0) {
+    if (!bad && rho < kFloorZone) {
       if (rho < s.stall_ratio * best) {
         best = rho;
         stale = 0;

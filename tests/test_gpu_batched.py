@@ -182,6 +182,25 @@ def test_batched_full_recipe_2000(ipr):
         say("full batch", kw, "OK", n_ok, "of", len(items), "worst rel err", worst)
 
 
+@pytest.mark.parametrize("tile", [0, 32])
+def test_batched_largest_orders(ipr, tile):
+    # the largest order the batched solver takes (1024), an odd one beside it,
+    # and the smallest, packed at odd offsets: every root against the definition
+    ns = [1, 1024, 1023, 2, 3]
+    ps = [3, 2, 1, 4, 2]
+    mats = [w.batch_matrix(n, 1e3, 77 + i)[0] for i, n in enumerate(ns)]
+    buf, offs = _pack(mats)
+    s = ipr.ipr_schedule_default(tile=tile, scale_squarings=6, dynamic_scaling=1)
+    C, res = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10, schedule=s)
+    cs = _unpack(host(C), offs, ns)
+    for n, p, a, c, r in zip(ns, ps, mats, cs, res):
+        err = it.rel_fro(c, it.eig_root(a, p))
+        say("largest orders: tile", tile, "n", n, "p", p, "status", r.status, "iters",
+            r.iters_fp64, "rel err", err)
+        assert r.status == ipr.IPR_OK, (n, p, r.as_dict())
+        assert err <= 1e-10 and np.array_equal(c, c.T)
+
+
 def test_batched_argument_errors(ipr):
     buf, offs = _pack([np.eye(4)])
     with pytest.raises(ipr.IprError):

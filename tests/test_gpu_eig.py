@@ -1,5 +1,5 @@
 """GPU parity of the symmetric eigenvalue solver (ipr_eigvalsh: Householder
-tridiagonalisation and Sturm bisection) against the oracle (oracle/eig.py),
+tridiagonalisation and Sturm multisection) against the oracle (oracle/eig.py),
 closed forms, and the generalised eigenvalues of the Loewdin problem."""
 import math
 
@@ -36,6 +36,19 @@ def test_random_symmetric(ipr, n):
     ref = eig.eigenvalues(a)
     assert np.all(np.diff(got) >= 0)
     assert np.max(np.abs(got - ref)) <= bound(n, ref), np.max(np.abs(got - ref))
+
+
+def test_bench_order_4096(ipr):
+    # the order the bench's Loewdin section solves, against LAPACK's values
+    n = 4096
+    rng = np.random.default_rng(4096)
+    x = rng.standard_normal((n, n))
+    a = x + x.T
+    got = host(ipr.ipr_eigvalsh(dev(a)))
+    ref = eig.eigenvalues(a)
+    say("eigvalsh n 4096: max error", np.max(np.abs(got - ref)), "bound", bound(n, ref))
+    assert np.all(np.diff(got) >= 0)
+    assert np.max(np.abs(got - ref)) <= bound(n, ref)
 
 
 def test_closed_forms_and_degenerate_spectra(ipr):

@@ -134,6 +134,46 @@ def test_residual_map_closed_forms():
         assert np.all(g >= 0) and np.all(g < np.abs(r[r != 0]))
 
 
+def test_step_contraction_below_one_half():
+    # p = 1: 1 - m(2 - m) = e^2, so the ratio is |e| and peaks at 1/2.
+    # p = 2: 1 - m((3 - m)/2)^2 = e^2 (3 + e)/4 with m = 1 - e, peaking at
+    # e = 1/2 with 7/16. Every p keeps |e| <= 1/2 to at most half of it, which
+    # is what lets the floor rule count only below FLOOR_ZONE.
+    assert it.step_contraction(1) == pytest.approx(0.5, abs=1e-12)
+    assert it.step_contraction(2) == pytest.approx(7.0 / 16.0, abs=1e-12)
+    for p in range(1, 9):
+        assert it.step_contraction(p) <= 0.5 + 1e-12
+    assert it.FLOOR_ZONE == 0.5
+    # Above 1/2 a step can keep most of the error: e = 0.99 with p = 1 keeps 99%.
+    assert it.step_contraction(1, emax=0.99) > 0.98
+
+
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_tiny_orders_converge_through_the_slow_phase(n, p):
+    # With kappa = 1e3 and n <= 3 the smallest eigenvalue alone sets the
+    # residual through its slow phase, which stays above 1/2 for several steps
+    # without halving; the run must still reach the tolerance.
+    for seed in range(4):
+        a, _, _ = _spd(n, 1e3, seed)
+        res = it.solve(a, p, 1e-10)
+        assert res.status == it.OK
+        # residual r < 1e-10 gives C = A^{-1/p}(I - r)^{1/p}: error below r/p
+        assert it.rel_fro(res.c, it.eig_root(a, p)) < 1e-10
+
+
+def test_floor_rule_over_the_whole_range_misfires():
+    # Counting stagnation anywhere below 1 ends this run in its slow phase.
+    a, _, _ = _spd(2, 1e3, 0)
+    saved = it.FLOOR_ZONE
+    try:
+        it.FLOOR_ZONE = 1.0
+        res = it.solve(a, 2, 1e-10)
+    finally:
+        it.FLOOR_ZONE = saved
+    assert res.status == it.EFLOOR and res.residual_true > 0.1
+
+
 @pytest.mark.parametrize("p", [2, 3])
 def test_invariants_symmetric_and_commuting(p):
     a, _, _ = _spd(128, 1e3, 12)
