@@ -6,11 +6,11 @@
 //     part of column k below the diagonal, H = I - tau v v^T maps x to
 //     beta e_1; the trailing matrix B becomes H B H = B - v w^T - w v^T with
 //     p = tau B v and w = p - (tau / 2)(p . v) v. The trailing matrix is kept
-//     whole (both triangles), so every access is a row access. Two launches
-//     per column, the update of one column fused with the product of the
-//     next (look-ahead): the first row of the updated block, and from it the
-//     next reflector (one workgroup); then the other rows, each updated and
-//     at once multiplied by the next reflector (one wave per row). HBM-bound:
+//     whole (both triangles), so every access is a row access. One launch per
+//     column, the update of one column fused with the reflector and product
+//     of the next (look-ahead): one wave per row streams the row once,
+//     updating it and at once multiplying it by the next reflector, which
+//     every wave forms for itself from the block's first row. HBM-bound:
 //     one read and one write of (n - k)^2 doubles per column, 16 n^3 / 3
 //     bytes in all.
 //  2. Multisection on the Sturm count of the tridiagonal matrix (d, e), one
@@ -98,100 +98,128 @@ __global__ __launch_bounds__(NT) void trail_gemv_kernel(const double* __restrict
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Look-ahead step after column k (trailing block B of order m = n - k - 1,
-// reflector V, tau, P = tau B V with partials): row 0 of B (row k + 1 of T)
-// is updated, B_0j -= V_0 W_j + W_0 V_j with W = P - c V, c = (tau / 2) P . V,
-// and the reflector of column k + 1 is formed from it: V2, tau2, d[k + 1],
-// e[k + 1]. One workgroup; each thread reads back only the row entries it
-// wrote itself.
-__global__ __launch_bounds__(NT) void next_reflector_kernel(
+// Threads of the column step below (one wave per row), and the entries each
+// lane loads before it computes on them (so that as many loads are in
+// flight: a wave's row streams from memory at the rate its loads in flight
+// allow).
+constexpr int NTC = 512;
+constexpr int UC = 8;
+
+// w_j = P_j - c V_j, and entry (i, j) of the trailing block after the rank-2
+// update, B_ij - (V_i w_j + w_i V_j). Every use goes through these two, with
+// the fused multiply-adds written out, so that each workgroup forms the same
+// bits for the same entry.
+__device__ __forceinline__ double w_of(double pj, double vj, double c) {
+  return __builtin_fma(-c, vj, pj);
+}
+__device__ __forceinline__ double rank2(double b, double vi, double wi, double vj, double wj) {
+  return b - __builtin_fma(vi, wj, wi * vj);
+}
+
+// Column k's step (trailing block B of order m = n - k - 1 >= 2, reflector V,
+// tau, P = tau B V with per-workgroup partials of P . V), with the next
+// column's reflector and product folded in (look-ahead). With W = P - c V,
+// c = (tau / 2) P . V, the update is B_ij -= V_i W_j + W_i V_j; the next
+// reflector comes from x = row 0 of the updated block beyond its first entry
+// (alpha = x_1, beta = -sign(alpha) |x|, V2 = (x - beta e_1) / (alpha - beta)).
+// One wave per row i = 1 .. m-1, each streaming its row once:
+//  * it updates B_ij (column 0 is not read again) and, from row 0 (which no
+//    wave writes: no later step reads row k + 1 of T), forms the updated x_j
+//    on the fly, accumulating |x|^2 beyond x_1 and sum_{j >= 2} B_ij x_j;
+//  * so every wave knows beta and the scale 1 / (alpha - beta) at the end of
+//    its row, identically (same code, same order), and
+//    P2[i - 1] = tau2 sum_j B_ij V2[j - 1] = tau2 (B_i1 + sum_{j >= 2} B_ij x_j / (alpha - beta));
+//  * it stores V2[i - 1]; the wave of row 1 stores tau2, d[k + 1], e[k + 1].
+// partial2[b] = sum over workgroup b's rows of P2 V2. One launch per column,
+// and no wave waits for another beyond the sum of the partials.
+__global__ __launch_bounds__(NTC) void column_step_kernel(
     double* __restrict__ T, int n, int k, const double* __restrict__ V,
     const double* __restrict__ P, const double* __restrict__ tau,
     const double* __restrict__ partial, int nparts, double* __restrict__ V2,
-    double* __restrict__ d, double* __restrict__ e, double* __restrict__ tau2) {
-  __shared__ double red[NT / 64];
-  __shared__ double head[2];  // updated B_00 and B_01
-  __shared__ double coef[2];
+    double* __restrict__ d, double* __restrict__ e, double* __restrict__ tau2,
+    double* __restrict__ P2, double* __restrict__ partial2) {
+  constexpr int NW = NTC / 64;
+  __shared__ double red[NW];
   const int m = n - k - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // workgroup sum in a fixed order, returned to every thread
+  auto wg_sum = [&](double v) {
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += red[w];
+    __syncthreads();  // (red is reused)
+    return t;
+  };
   double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += NT) s += partial[b];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  const double c = 0.5 * *tau * ((red[0] + red[1]) + (red[2] + red[3]));
-  __syncthreads();  // (red is reused below)
-  const double v0 = V[0], w0 = P[0] - c * V[0];
-  double* row = T + (size_t)(k + 1) * n + k + 1;
-  double q = 0.0;  // |x|^2 beyond its first entry, x = B_0j for j = 1 .. m-1
-  for (int j = threadIdx.x; j < m; j += NT) {
-    const double t = row[j] - (v0 * (P[j] - c * V[j]) + w0 * V[j]);
-    row[j] = t;
-    if (j < 2)
-      head[j] = t;
-    else
-      q += t * t;
-  }
-  q = wave_sum(q);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double xnorm2 = (red[0] + red[1]) + (red[2] + red[3]);
-    const double alpha = head[1];
-    d[k + 1] = head[0];
-    if (xnorm2 == 0.0) {
-      e[k + 1] = alpha;
-      *tau2 = 0.0;
-      coef[0] = 0.0;
-    } else {
-      const double beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      e[k + 1] = beta;
-      *tau2 = (beta - alpha) / beta;
-      coef[0] = 1.0 / (alpha - beta);
-    }
-  }
-  __syncthreads();
-  const double cf = coef[0];
-  for (int j = threadIdx.x; j < m; j += NT)
-    if (j >= 1) V2[j - 1] = j == 1 ? 1.0 : row[j] * cf;
-}
-
-// Rows 1 .. m-1 of the trailing block B of column k, one wave per row: the
-// rank-2 update of columns 1 .. m-1 (column 0 is not read again), and in the
-// same pass P2[i - 1] = tau2 sum_j B_ij V2[j - 1], the next column's
-// product; partial2[b] = sum over the workgroup's rows of P2 V2.
-__global__ __launch_bounds__(NT) void update_gemv_kernel(
-    double* __restrict__ T, int n, int k, const double* __restrict__ V,
-    const double* __restrict__ P, const double* __restrict__ tau,
-    const double* __restrict__ partial, int nparts, const double* __restrict__ V2,
-    const double* __restrict__ tau2, double* __restrict__ P2, double* __restrict__ partial2) {
-  __shared__ double red[NT / 64];
-  const int m = n - k - 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += NT) s += partial[b];
-  s = wave_sum(s);
-  if (lane == 0) red[wave] = s;
-  __syncthreads();
-  const double c = 0.5 * *tau * ((red[0] + red[1]) + (red[2] + red[3]));
-  __syncthreads();  // (red is reused below)
-  const int i = 1 + blockIdx.x * (NT / 64) + wave;
+  for (int b = tid; b < nparts; b += NTC) s += partial[b];
+  const double c = 0.5 * *tau * wg_sum(s);
+  const double v0 = V[0], w0 = w_of(P[0], V[0], c);
+  const double* row0 = T + (size_t)(k + 1) * n + k + 1;
+  const int i = 1 + blockIdx.x * NW + wave;
   double pv = 0.0;
   if (i < m) {
-    const double vi = V[i], wi = P[i] - c * V[i];
+    const double vi = V[i], wi = w_of(P[i], vi, c);
     double* row = T + (size_t)(k + 1 + i) * n + k + 1;
-    double acc = 0.0;
-    for (int j = 1 + lane; j < m; j += 64) {
-      const double t = row[j] - (vi * (P[j] - c * V[j]) + wi * V[j]);
-      row[j] = t;
-      acc += t * V2[j - 1];
+    double acc = 0.0, q = 0.0, b1 = 0.0, x1 = 0.0;
+    for (int j0 = 1 + lane; j0 < m; j0 += 64 * UC) {
+      // all loads of UC entries first, so that they are in flight together
+      double rr[UC], r0[UC], vv[UC], pp[UC];
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int j = j0 + 64 * u;
+        const bool in = j < m;
+        rr[u] = in ? row[j] : 0.0;
+        r0[u] = in ? row0[j] : 0.0;
+        vv[u] = in ? V[j] : 0.0;
+        pp[u] = in ? P[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        const int j = j0 + 64 * u;
+        if (j < m) {
+          const double wj = w_of(pp[u], vv[u], c);
+          const double t = rank2(rr[u], vi, wi, vv[u], wj);
+          row[j] = t;
+          const double x = rank2(r0[u], v0, w0, vv[u], wj);
+          if (j == 1) {
+            b1 = t;
+            x1 = x;
+          } else {
+            acc += t * x;
+            q += x * x;
+          }
+        }
+      }
     }
-    acc = wave_sum(acc) * *tau2;
-    if (lane == 0) P2[i - 1] = acc;
-    pv = acc * V2[i - 1];
+    // (b1 and x1 are nonzero in lane 0 only: their wave sums are exact copies)
+    acc = wave_sum(acc);
+    q = wave_sum(q);
+    b1 = wave_sum(b1);
+    const double alpha = wave_sum(x1);
+    double beta = alpha, t2 = 0.0, cf = 0.0;  // q == 0: already reduced, H = I
+    if (q != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + q), alpha);
+      t2 = (beta - alpha) / beta;
+      cf = 1.0 / (alpha - beta);
+    }
+    const double p2 = t2 * __builtin_fma(acc, cf, b1);
+    const double v2i = i == 1 ? 1.0 : rank2(row0[i], v0, w0, vi, wi) * cf;
+    if (lane == 0) {
+      P2[i - 1] = p2;
+      V2[i - 1] = v2i;
+      if (i == 1) {
+        d[k + 1] = rank2(row0[0], v0, w0, v0, w0);
+        e[k + 1] = beta;
+        *tau2 = t2;
+      }
+      pv = p2 * v2i;
+    }
   }
-  if (lane == 0) red[wave] = pv;
-  __syncthreads();
-  if (threadIdx.x == 0) partial2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  const double ps = wg_sum(pv);
+  if (tid == 0) partial2[blockIdx.x] = ps;
 }
 
 // d[n-1] = T[n-1][n-1] (the last diagonal entry, untouched by reflectors).
@@ -300,8 +328,9 @@ int ipr_eigvalsh(const double* dA, int n, double* dW, void* dWork, size_t work_b
   HIP_TRY(hipMemcpyAsync(w.T, dA, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice,
                          stream));
   if (n >= 2) {
-    // column 0: its reflector and product; then, per column k, the update of
-    // its block fused with the next column's reflector and product
+    // column 0: its reflector and product; then, per column k, one launch:
+    // the update of its block fused with the next column's reflector and
+    // product
     hipLaunchKernelGGL(reflector_kernel, dim3(1), dim3(NT), 0, stream, w.T, n, 0, w.V[0], w.d,
                        w.e, w.tau[0]);
     HIP_TRY(hipGetLastError());
@@ -311,14 +340,10 @@ int ipr_eigvalsh(const double* dA, int n, double* dW, void* dWork, size_t work_b
     HIP_TRY(hipGetLastError());
     for (int k = 0; k + 3 <= n; ++k) {
       const int m = n - k - 1, a = k & 1, b = a ^ 1;
-      hipLaunchKernelGGL(next_reflector_kernel, dim3(1), dim3(NT), 0, stream,
-                         w.T, n, k, w.V[a], w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d,
-                         w.e, w.tau[b]);
-      HIP_TRY(hipGetLastError());
-      const int nb = (m - 1 + NT / 64 - 1) / (NT / 64);
-      hipLaunchKernelGGL(update_gemv_kernel, dim3(nb), dim3(NT), 0, stream, w.T, n, k, w.V[a],
-                         w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.tau[b], w.P[b],
-                         w.partial[b]);
+      const int nb = (m - 1 + NTC / 64 - 1) / (NTC / 64);
+      hipLaunchKernelGGL(column_step_kernel, dim3(nb), dim3(NTC), 0, stream, w.T, n, k, w.V[a],
+                         w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d, w.e, w.tau[b],
+                         w.P[b], w.partial[b]);
       HIP_TRY(hipGetLastError());
       nparts = nb;
     }
