@@ -98,12 +98,18 @@ __global__ __launch_bounds__(NT) void trail_gemv_kernel(const double* __restrict
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Threads of the column step below (one wave per row), and the entries each
-// lane loads before it computes on them (so that as many loads are in
-// flight: a wave's row streams from memory at the rate its loads in flight
-// allow).
+// Threads of the column step below, and the entries of each row a lane loads
+// before it computes on them (so that as many loads are in flight: a row
+// streams from memory at the rate its loads in flight allow).
 constexpr int NTC = 512;
 constexpr int UC = 8;
+// Blocks of a larger order take two (four) rows per wave: the loads of row 0,
+// V and P then serve several rows, and there are still enough waves to keep
+// every CU streaming (measured at n = 8192: 872 ms with one row per wave,
+// 772 ms with two above 2048, 713 ms with four above 4096; two rows from
+// 1024 on made n = 2048 slower, 28.2 against 25.0 ms).
+constexpr int kRows2 = 2048;
+constexpr int kRows4 = 4096;
 
 // w_j = P_j - c V_j, and entry (i, j) of the trailing block after the rank-2
 // update, B_ij - (V_i w_j + w_i V_j). Every use goes through these two, with
@@ -122,7 +128,8 @@ __device__ __forceinline__ double rank2(double b, double vi, double wi, double v
 // c = (tau / 2) P . V, the update is B_ij -= V_i W_j + W_i V_j; the next
 // reflector comes from x = row 0 of the updated block beyond its first entry
 // (alpha = x_1, beta = -sign(alpha) |x|, V2 = (x - beta e_1) / (alpha - beta)).
-// One wave per row i = 1 .. m-1, each streaming its row once:
+// RW rows i = 1 .. m-1 per wave (rows w and w + 8 of the workgroup's 8 RW),
+// each streamed once:
 //  * it updates B_ij (column 0 is not read again) and, from row 0 (which no
 //    wave writes: no later step reads row k + 1 of T), forms the updated x_j
 //    on the fly, accumulating |x|^2 beyond x_1 and sum_{j >= 2} B_ij x_j;
@@ -132,6 +139,7 @@ __device__ __forceinline__ double rank2(double b, double vi, double wi, double v
 //  * it stores V2[i - 1]; the wave of row 1 stores tau2, d[k + 1], e[k + 1].
 // partial2[b] = sum over workgroup b's rows of P2 V2. One launch per column,
 // and no wave waits for another beyond the sum of the partials.
+template <int RW>
 __global__ __launch_bounds__(NTC) void column_step_kernel(
     double* __restrict__ T, int n, int k, const double* __restrict__ V,
     const double* __restrict__ P, const double* __restrict__ tau,
@@ -158,20 +166,34 @@ __global__ __launch_bounds__(NTC) void column_step_kernel(
   const double c = 0.5 * *tau * wg_sum(s);
   const double v0 = V[0], w0 = w_of(P[0], V[0], c);
   const double* row0 = T + (size_t)(k + 1) * n + k + 1;
-  const int i = 1 + blockIdx.x * NW + wave;
+  const int ibase = 1 + blockIdx.x * NW * RW + wave;
   double pv = 0.0;
-  if (i < m) {
-    const double vi = V[i], wi = w_of(P[i], vi, c);
-    double* row = T + (size_t)(k + 1 + i) * n + k + 1;
-    double acc = 0.0, q = 0.0, b1 = 0.0, x1 = 0.0;
+  if (ibase < m) {
+    int ii[RW];
+    bool ok[RW];
+    double vi[RW], wi[RW], acc[RW], b1[RW];
+    double* row[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      ii[r] = ibase + r * NW;
+      ok[r] = ii[r] < m;
+      const int ic = ok[r] ? ii[r] : ibase;  // (a row past the block is not touched)
+      vi[r] = V[ic];
+      wi[r] = w_of(P[ic], vi[r], c);
+      row[r] = T + (size_t)(k + 1 + ic) * n + k + 1;
+      acc[r] = 0.0;
+      b1[r] = 0.0;
+    }
+    double q = 0.0, x1 = 0.0;
     for (int j0 = 1 + lane; j0 < m; j0 += 64 * UC) {
       // all loads of UC entries first, so that they are in flight together
-      double rr[UC], r0[UC], vv[UC], pp[UC];
+      double rr[RW][UC], r0[UC], vv[UC], pp[UC];
 #pragma unroll
       for (int u = 0; u < UC; ++u) {
         const int j = j0 + 64 * u;
         const bool in = j < m;
-        rr[u] = in ? row[j] : 0.0;
+#pragma unroll
+        for (int r = 0; r < RW; ++r) rr[r][u] = in && ok[r] ? row[r][j] : 0.0;
         r0[u] = in ? row0[j] : 0.0;
         vv[u] = in ? V[j] : 0.0;
         pp[u] = in ? P[j] : 0.0;
@@ -181,23 +203,21 @@ __global__ __launch_bounds__(NTC) void column_step_kernel(
         const int j = j0 + 64 * u;
         if (j < m) {
           const double wj = w_of(pp[u], vv[u], c);
-          const double t = rank2(rr[u], vi, wi, vv[u], wj);
-          row[j] = t;
           const double x = rank2(r0[u], v0, w0, vv[u], wj);
-          if (j == 1) {
-            b1 = t;
-            x1 = x;
-          } else {
-            acc += t * x;
-            q += x * x;
+          if (j == 1) x1 = x; else q += x * x;
+#pragma unroll
+          for (int r = 0; r < RW; ++r) {
+            if (ok[r]) {
+              const double t = rank2(rr[r][u], vi[r], wi[r], vv[u], wj);
+              row[r][j] = t;
+              if (j == 1) b1[r] = t; else acc[r] += t * x;
+            }
           }
         }
       }
     }
     // (b1 and x1 are nonzero in lane 0 only: their wave sums are exact copies)
-    acc = wave_sum(acc);
     q = wave_sum(q);
-    b1 = wave_sum(b1);
     const double alpha = wave_sum(x1);
     double beta = alpha, t2 = 0.0, cf = 0.0;  // q == 0: already reduced, H = I
     if (q != 0.0) {
@@ -205,17 +225,25 @@ __global__ __launch_bounds__(NTC) void column_step_kernel(
       t2 = (beta - alpha) / beta;
       cf = 1.0 / (alpha - beta);
     }
-    const double p2 = t2 * __builtin_fma(acc, cf, b1);
-    const double v2i = i == 1 ? 1.0 : rank2(row0[i], v0, w0, vi, wi) * cf;
-    if (lane == 0) {
-      P2[i - 1] = p2;
-      V2[i - 1] = v2i;
-      if (i == 1) {
-        d[k + 1] = rank2(row0[0], v0, w0, v0, w0);
-        e[k + 1] = beta;
-        *tau2 = t2;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const double a = wave_sum(acc[r]);
+      const double bb = wave_sum(b1[r]);
+      if (ok[r]) {
+        const int i = ii[r];
+        const double p2 = t2 * __builtin_fma(a, cf, bb);
+        const double v2i = i == 1 ? 1.0 : rank2(row0[i], v0, w0, vi[r], wi[r]) * cf;
+        if (lane == 0) {
+          P2[i - 1] = p2;
+          V2[i - 1] = v2i;
+          if (i == 1) {
+            d[k + 1] = rank2(row0[0], v0, w0, v0, w0);
+            e[k + 1] = beta;
+            *tau2 = t2;
+          }
+          pv += p2 * v2i;
+        }
       }
-      pv = p2 * v2i;
     }
   }
   const double ps = wg_sum(pv);
@@ -340,10 +368,22 @@ int ipr_eigvalsh(const double* dA, int n, double* dW, void* dWork, size_t work_b
     HIP_TRY(hipGetLastError());
     for (int k = 0; k + 3 <= n; ++k) {
       const int m = n - k - 1, a = k & 1, b = a ^ 1;
-      const int nb = (m - 1 + NTC / 64 - 1) / (NTC / 64);
-      hipLaunchKernelGGL(column_step_kernel, dim3(nb), dim3(NTC), 0, stream, w.T, n, k, w.V[a],
-                         w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d, w.e, w.tau[b],
-                         w.P[b], w.partial[b]);
+      // several rows per wave share the loads of row 0, V and P once the
+      // block is large enough to keep every CU busy with fewer waves
+      const int rw = m > kRows4 ? 4 : m > kRows2 ? 2 : 1;
+      const int nb = (m - 1 + NTC / 64 * rw - 1) / (NTC / 64 * rw);
+      if (rw == 4)
+        hipLaunchKernelGGL(column_step_kernel<4>, dim3(nb), dim3(NTC), 0, stream, w.T, n, k,
+                           w.V[a], w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d, w.e,
+                           w.tau[b], w.P[b], w.partial[b]);
+      else if (rw == 2)
+        hipLaunchKernelGGL(column_step_kernel<2>, dim3(nb), dim3(NTC), 0, stream, w.T, n, k,
+                           w.V[a], w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d, w.e,
+                           w.tau[b], w.P[b], w.partial[b]);
+      else
+        hipLaunchKernelGGL(column_step_kernel<1>, dim3(nb), dim3(NTC), 0, stream, w.T, n, k,
+                           w.V[a], w.P[a], w.tau[a], w.partial[a], nparts, w.V[b], w.d, w.e,
+                           w.tau[b], w.P[b], w.partial[b]);
       HIP_TRY(hipGetLastError());
       nparts = nb;
     }

@@ -51,6 +51,20 @@ def test_bench_order_4096(ipr):
     assert np.max(np.abs(got - ref)) <= bound(n, ref)
 
 
+def test_all_row_tiers_of_the_column_step(ipr):
+    # trailing blocks above order 4096 take four rows per wave, above 2048 two,
+    # then one: n = 4500 runs through all three
+    n = 4500
+    rng = np.random.default_rng(4500)
+    x = rng.standard_normal((n, n))
+    a = x + x.T
+    got = host(ipr.ipr_eigvalsh(dev(a)))
+    ref = eig.eigenvalues(a)
+    say("eigvalsh n 4500: max error", np.max(np.abs(got - ref)), "bound", bound(n, ref))
+    assert np.all(np.diff(got) >= 0)
+    assert np.max(np.abs(got - ref)) <= bound(n, ref)
+
+
 def test_closed_forms_and_degenerate_spectra(ipr):
     n = 1000
     t = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
