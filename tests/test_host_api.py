@@ -121,3 +121,56 @@ def test_lowdin_rejects_aliasing_and_short_workspace():
              None) == ipr.IPR_EARG
     assert f(FAKE_A, H, X, Ht, 64, 1e-10, ct.byref(s), ct.byref(res), FAKE_W, 64,
              None) == ipr.IPR_EARG
+
+
+def test_eigvalsh_checks_arguments_and_workspace_before_any_device_call():
+    f = binding._fn("ipr_eigvalsh")
+    ws = binding._fn("ipr_eigvalsh_workspace")
+    assert ws(0) == 0 and ws(-3) == 0
+    # the working copy of A dominates: at least n^2 doubles, growing with n
+    assert ws(100) >= 100 * 100 * 8 and ws(1000) >= 1000 * 1000 * 8 and ws(1000) > ws(100)
+    W = ct.c_void_p(32768)
+    assert f(None, 64, W, FAKE_W, 1 << 30, None) == ipr.IPR_EARG
+    assert f(FAKE_A, 64, None, FAKE_W, 1 << 30, None) == ipr.IPR_EARG
+    assert f(FAKE_A, 64, W, None, 1 << 30, None) == ipr.IPR_EARG
+    assert f(FAKE_A, 0, W, FAKE_W, 1 << 30, None) == ipr.IPR_EARG
+    assert f(FAKE_A, 64, W, FAKE_W, ws(64) - 512, None) == ipr.IPR_EARG
+    assert "workspace too small" in ipr.ipr_last_error()
+
+
+def test_noalloc_rejects_what_it_cannot_hold_before_any_device_call():
+    f = binding._fn("ipr_solve_noalloc")
+    res = ipr.IprResult()
+
+    def rc(n, p=2, **kw):
+        s = ipr.ipr_schedule_default(**kw)
+        return f(FAKE_A, FAKE_C, n, p, 1e-10, ct.byref(s), ct.byref(res), None)
+
+    assert rc(0) == ipr.IPR_EARG
+    assert rc(64, p=0) == ipr.IPR_EARG and rc(64, p=65) == ipr.IPR_EARG
+    assert rc(64, timing=1) == ipr.IPR_EARG
+    assert rc(4096) == ipr.IPR_EARG
+    assert "fixed scratch" in ipr.ipr_last_error()
+
+
+def test_batched_rejects_bad_arguments_before_any_device_call():
+    f = binding._fn("ipr_solve_batched")
+    offs = (ct.c_int64 * 2)(0, 64 * 64)
+    ns = (ct.c_int * 2)(64, 64)
+    ps = (ct.c_int * 2)(2, 2)
+
+    def rc(batch=2, tol=1e-10, n=None, p=None, o=None, **kw):
+        s = ipr.ipr_schedule_default(**kw)
+        return f(FAKE_A, FAKE_C, o or offs, n or ns, p or ps, batch, tol, ct.byref(s), None,
+                 FAKE_W, 1 << 40, None)
+
+    assert rc(batch=0) == ipr.IPR_EARG
+    assert rc(tol=0.0) == ipr.IPR_EARG and rc(tol=float("nan")) == ipr.IPR_EARG
+    assert rc(init=ipr.IPR_INIT_PAPER_EQ3) == ipr.IPR_EARG
+    assert rc(bulk_dtype=ipr.IPR_FP16) == ipr.IPR_EARG
+    assert rc(tile=48) == ipr.IPR_EARG
+    assert rc(max_iter=-1) == ipr.IPR_EARG
+    assert rc(n=(ct.c_int * 2)(64, 1025)) == ipr.IPR_EARG
+    assert rc(p=(ct.c_int * 2)(0, 2)) == ipr.IPR_EARG and rc(p=(ct.c_int * 2)(2, 9)) == ipr.IPR_EARG
+    assert rc(o=(ct.c_int64 * 2)(0, -1)) == ipr.IPR_EARG
+    assert "item 1" in ipr.ipr_last_error()
