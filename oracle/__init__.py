@@ -16,7 +16,9 @@ Parity pins (tests marked "not gpu" check each of these):
                          hand-worked 2x2 closed form, diagonal closed form.
   * ``solve``          - against eig_root, numpy.linalg.inv (p = 1), the
                          scalar recursion on diagonal and scaled-identity A
-                         (bit for bit), spectral iteration counts, invariants.
+                         (bit for bit), spectral iteration counts, invariants;
+                         its floor rule's zone against the closed forms of
+                         one step's contraction (p = 1, 2).
   * ``spectral_count`` - against the dense iteration's count.
   * rounding emulator  - against torch dtype casts (bf16, fp16, fp8 e4m3).
   * MLP forward/back   - backward against central finite differences; GELU

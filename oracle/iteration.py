@@ -21,6 +21,9 @@ Readings of what the paper leaves open (each is listed in the design notes):
   * stopping: the Frobenius norm of I - M_k below tol, confirmed by the
     directly computed ||I - C_k^p A||_F below tol.
   * every iterate is symmetrised, X <- (X + X^T)/2.
+  * precision floor: reported once the residual, below 1/2, has not halved
+    its best value for floor_window iterations (below 1/2 every exact step
+    at least halves it: ``step_contraction``).
 """
 from __future__ import annotations
 
