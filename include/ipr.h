@@ -220,8 +220,9 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol,
 /* Eigenvalues of a dense symmetric matrix, ascending: the step after the
  * Loewdin transform (Section IV-A: the eigenvalues of X H X, X = S^{-1/2},
  * are those of H c = e S c). Householder reduction to tridiagonal form (one
- * reflector per column, the trailing matrix kept whole) and bisection on the
- * Sturm count of the tridiagonal matrix, FP64 throughout.
+ * reflector per column, the trailing matrix kept whole) and multisection
+ * (bisection at 64 points per round) on the Sturm count of the tridiagonal
+ * matrix, FP64 throughout.
  *   dA    device, n x n float64, symmetric (read only)
  *   dW    device, n float64: the eigenvalues in ascending order
  *   dWork device workspace of work_bytes >= ipr_eigvalsh_workspace(n)
