@@ -31,7 +31,7 @@ class IprSchedule(ct.Structure):
                 ("emul_slices", ct.c_int), ("store_format", ct.c_int),
                 ("store_bits", ct.c_int), ("store_regime", ct.c_int),
                 ("hist_ref", ct.c_void_p), ("hist_err", ct.c_void_p), ("hist_rho", ct.c_void_p),
-                ("hist_len", ct.c_int), ("bulk_force", ct.c_int)]
+                ("hist_len", ct.c_int), ("bulk_force", ct.c_int), ("scale_lanczos", ct.c_int)]
 
 
 class IprResult(ct.Structure):

@@ -208,6 +208,8 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
   if (s.tile != 0 && !valid_tile(s.tile))
     return fail(IPR_EARG, "ipr_solve_batched: tile must be 0, 32 or 64");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve_batched: max_iter < 0");
+  if (s.scale_lanczos)
+    return fail(IPR_EARG, "ipr_solve_batched: scale_lanczos is an ipr_solve option");
   int tiles[IPR_BATCH_BUCKETS];
   ipr_get_batched_tiles(tiles);
   std::vector<BatchItem> items(batch);

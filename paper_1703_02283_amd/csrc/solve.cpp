@@ -839,7 +839,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     if (s.store_format == IPR_STORE_FIXED && (s.store_bits < 1 || s.store_bits > 64))
       return fail(IPR_EARG, "ipr_solve: store_bits must be 1..64 fractional bits");
     if (s.init != IPR_INIT_IDENTITY || s.evaluation != IPR_EVAL_COUPLED ||
-        s.bulk_dtype != IPR_FP64 || s.scale_squarings || s.dynamic_scaling)
+        s.bulk_dtype != IPR_FP64 || s.scale_squarings || s.scale_lanczos ||
+        s.dynamic_scaling)
       return fail(IPR_EARG, "ipr_solve: approximate storage runs the plain coupled iteration "
                   "from the scaled identity in FP64 (no squarings, no scaled steps)");
   }
@@ -848,6 +849,9 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   if (s.store_regime == 1 && !store)
     return fail(IPR_EARG, "ipr_solve: the all-arithmetic regime needs a store_format");
   if (s.hist_len < 0) return fail(IPR_EARG, "ipr_solve: hist_len < 0");
+  if (s.scale_squarings > 0 && s.scale_lanczos)
+    return fail(IPR_EARG, "ipr_solve: scale_squarings and scale_lanczos are two ways to the "
+                "same scale: choose one");
   if (s.init == IPR_INIT_LEARNED && !s.mlp_params)
     return fail(IPR_EARG, "ipr_solve: the learned start needs schedule.mlp_params");
 
@@ -915,6 +919,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   // spectrum of A / sc inside (0, 1]; then M_0 = C_0^p A and N_0.
   double b[3] = {1.0, 0.0, 0.0};
   double sc = sigma;            // ||A||_2 <= sqrt(||A||_1 ||A||_inf)
+  double lz_lo = 0.0;           // lambda_min estimate of a Lanczos run made for the scale
   const double* G = nullptr;    // A^2 when the learned start computed it
   int init = s.init;
   if (init == IPR_INIT_POLY) {
@@ -952,6 +957,21 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       src = e.D;
     }
     sc = best;
+    res.init_scale = sc;
+  } else if (init == IPR_INIT_IDENTITY && s.scale_lanczos && n >= 32) {
+    // The scale from the largest Ritz value of the Lanczos run on A that the
+    // scaled steps take their lower end from (so it runs once, here): a Ritz
+    // value lies inside the spectrum, and the largest one approaches
+    // lambda_max from below within a fraction of a percent after 24 steps on
+    // spectra that are dense near their top; the 1% margin puts s at or above
+    // lambda_max in practice. No product is spent. It is not a certified
+    // bound: eq. (2) holds while lambda_max / s < 2, the scaled steps keep
+    // mu lambda_max / s below p + 1 unless s is off by more than 15%, and a
+    // run that diverges restarts from the norm-scaled identity.
+    double lo = 0.0, hi = 0.0;
+    if (int rc = sv.lanczos_range(dA, std::min(24, n - 8), w.m[0], &lo, &hi)) return rc;
+    if (hi > 0.0 && std::isfinite(hi)) sc = std::min(sigma, 1.01 * hi);
+    if (lo > 0.0 && std::isfinite(lo)) lz_lo = lo;
     res.init_scale = sc;
   } else if (init == IPR_INIT_LEARNED) {
     // Certified scale: lambda_max(A)^2 = lambda_max(A^2) <= sqrt(||A^2||_1 ||A^2||_inf),
@@ -1017,7 +1037,8 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
   // M_k by mu_k >= 1 (C_k by mu_k^{1/p}), chosen to lift the lower end. With
   // the start C_0 = sc^{-1/p} q(A / sc) (the scaled identity: q = 1) the
   // eigenvalues of M_0 are phi(x) = q(x)^p x at x = lambda / sc in (0, 1]:
-  // the upper end is sup phi on (0, 1] (certified), the lower end the least
+  // the upper end is sup phi on (0, 1] (certified; with scale_lanczos, where
+  // sc is an estimate, held there all the same), the lower end the least
   // phi on [theta / sc, 1], theta a Lanczos estimate of lambda_min (from
   // above: an overestimate only makes the factors smaller). mu_k mod_b < 2
   // keeps every step inside eq. (2). Once the residual is below 1 it bounds
@@ -1029,8 +1050,9 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
              s.evaluation == IPR_EVAL_COUPLED && n >= 32;
   double mod_a = 0.0, mod_b = 1.0, mu_k = 1.0;
   if (dyn) {
-    double theta = 0.0;
-    if (int rc = sv.lanczos_min(std::min(24, n - 8), w.m[0], &theta)) return rc;
+    double theta = lz_lo;
+    if (!(theta > 0.0))
+      if (int rc = sv.lanczos_min(std::min(24, n - 8), w.m[0], &theta)) return rc;
     res.lmin_est = theta;
     dyn = theta > 0.0 && std::isfinite(theta) && std::isfinite(sup_phi) && sup_phi > 0.0;
     if (dyn) {

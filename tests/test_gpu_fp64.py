@@ -268,6 +268,34 @@ def test_dynamic_scaling(ipr, p, squarings):
     assert np.allclose(host(C), 2.5 ** (-1.0 / p) * np.eye(64), rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("dyn", [0, 1])
+def test_lanczos_scale(ipr, p, dyn):
+    # the scale from the largest Ritz value of the Lanczos run, times 1.01: at
+    # most 1.01 lambda_max (a Ritz value lies inside the spectrum) and close to
+    # it; the same root; the oracle's count from the start s = 1.01 lambda_max
+    # (its own eigenvalues, nothing taken from the library)
+    say("lanczos scale p", p, "scaled steps", dyn)
+    n = 300
+    a, lam, _ = w.spd_log_spectrum(n, 1e4, seed=90 + p)
+    c, r = _solve(ipr, a, p, 1e-10, scale_lanczos=1, dynamic_scaling=dyn)
+    assert r.status == ipr.IPR_OK and r.fallback_used == 0
+    s_ref = 1.01 * lam.max()
+    assert 0.95 * s_ref <= r.init_scale <= s_ref * (1 + 1e-12)
+    assert it.rel_fro(c, it.eig_root(a, p)) <= 1e-10
+    if dyn:
+        ref = it.solve(a, p, 1e-10, scaled=s_ref)
+        assert ref.status == it.OK and -1 <= r.iters_fp64 - ref.iters <= SCALED_SLACK
+    else:
+        ref = it.solve(a, p, 1e-10, init=s_ref ** (-1.0 / p) * np.eye(n))
+        assert ref.status == it.OK and abs(r.iters_fp64 - ref.iters) <= 1
+    # below order 32 there is no Lanczos run: the norm bound of eq. (3)
+    a, lam, _ = w.spd_log_spectrum(24, 1e3, seed=5)
+    c, r = _solve(ipr, a, p, 1e-10, scale_lanczos=1, dynamic_scaling=dyn)
+    assert r.status == ipr.IPR_OK
+    assert r.init_scale == pytest.approx(np.sqrt(r.norm1 * r.norminf), rel=1e-15)
+
+
 def test_paper_eq3_start(ipr):
     # p = 1 from eq. (3) converges (Newton-Schulz); counts agree with the oracle
     a, _, _ = w.spd_log_spectrum(128, 1e2, seed=7)
