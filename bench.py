@@ -8,10 +8,10 @@ the residual from C and A. A is already resident in HBM when timing starts.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line. Besides the headline schedule (FP64, scaled-identity
-start whose scale is tightened by repeated squaring, dynamically scaled
-steps, triangle products) it times, outside the timed steps, the
-comparators: the same start with the plain steps of eq. (1), the
-norm-scaled identity, plain FP64 with full products, the eq. (3) start,
+start whose scale comes from the largest Ritz value of a Lanczos run on A,
+dynamically scaled steps, triangle products) it times, outside the timed
+steps, the comparators: the certified repeated-squaring scale with the same
+steps and with the plain steps of eq. (1), the norm-scaled identity, plain FP64 with full products, the eq. (3) start,
 low-precision bulk phases, FP64-accurate products from int8 digit slices,
 the learned start; the n = 4096 kernel matrix, the approximate-storage sweep
 at n = 768, the Loewdin transform at n = 4096 and the 2000-problem batch; and
@@ -181,6 +181,7 @@ def householder_kappa1e2_runs(ipr, torch, w, dev, tol, p=2, n=16384):
     C = torch.empty_like(A)
     out = {"workload": f"householder_spd n={n} p={p} kappa=100 seed=0", "tol": tol}
     for name, kw, dtn in (
+            ("fp64_lanczos_scale_scaled_steps", dict(scale_lanczos=1, dynamic_scaling=1), None),
             ("fp64_power_scale_scaled_steps", dict(scale_squarings=6, dynamic_scaling=1), None),
             ("fp64_identity_norm_scale", {}, None),
             ("fp16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP16, bulk_force=1), "fp16"),
@@ -355,7 +356,8 @@ def lowdin_runs(ipr, torch, w, dev, tol):
     del s, h
     out = {"workload": "overlap_and_hamiltonian n=4096 (box 20) seed=0, tol 1e-10"}
     for name, kw in (("fp64_default", {}),
-                     ("fp64_power_scale_scaled_steps", dict(scale_squarings=6, dynamic_scaling=1))):
+                     ("fp64_power_scale_scaled_steps", dict(scale_squarings=6, dynamic_scaling=1)),
+                     ("fp64_lanczos_scale_scaled_steps", dict(scale_lanczos=1, dynamic_scaling=1))):
         sch = ipr.ipr_schedule_default(timing=1, **kw)
         ipr.ipr_lowdin(S, H, tol, schedule=sch)   # warm-up
         torch.cuda.synchronize()
@@ -411,6 +413,8 @@ def batched_runs(ipr, torch, w, dev, tol, reps=3):
     log("batched tuned tiles", out["tuned_tiles"])
     for name, kw in (("fp64_power_scale_scaled_steps",
                       dict(scale_squarings=6, dynamic_scaling=1)),
+                     ("fp64_lanczos_scale_scaled_steps",
+                      dict(scale_lanczos=1, dynamic_scaling=1)),
                      ("fp64", {}), ("bf16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_BF16))):
         s = ipr.ipr_schedule_default(**kw)
         ipr.ipr_solve_batched(A, offs, ns, ps, tol, schedule=s, out=C)   # capture + warm-up
@@ -481,10 +485,11 @@ def main():
     A = torch.from_numpy(a_host).to(dev)
     del a_host
     C = torch.empty_like(A)
-    # the headline schedule: FP64, scaled identity whose scale is tightened by
-    # repeated squaring (certified bound on lambda_max), dynamically scaled
-    # steps (Lanczos estimate of lambda_min), triangle products
-    sched = ipr.ipr_schedule_default(timing=1, scale_squarings=6, dynamic_scaling=1)
+    # the headline schedule: FP64, scaled identity whose scale is the largest
+    # Ritz value of a 24-step Lanczos run on A (times 1.01), dynamically scaled
+    # steps (the same run's smallest Ritz value for the lower end), triangle
+    # products
+    sched = ipr.ipr_schedule_default(timing=1, scale_lanczos=1, dynamic_scaling=1)
     ws = torch.empty(ipr.ipr_workspace_size(n, p, 1, sched), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
@@ -528,9 +533,9 @@ def main():
         "config": {"workload": f"householder_spd n={n} p={p} kappa={args.kappa:g} "
                                f"seed={args.seed} tol={tol:g}",
                    "n": n, "p": p, "kappa": args.kappa, "tol": tol,
-                   "schedule": "fp64, scaled-identity start with the repeated-squaring scale "
-                               "(at most 6 squarings), dynamically scaled steps, triangle "
-                               "products"},
+                   "schedule": "fp64, scaled-identity start with the Lanczos scale (1.01 x "
+                               "the largest Ritz value of 24 steps), dynamically scaled steps, "
+                               "triangle products"},
         "solve": {"status_all_ok": ok, "iterations": last.iters_fp64, "gemms": last.gemms,
                   "init_scale": last.init_scale,
                   "residual_true": last.residual_true, "ms_norms": last.ms_norms,
@@ -575,6 +580,9 @@ def main():
             comps[name] = d
             return d
 
+        # the same scaled steps from the certified repeated-squaring scale
+        d = run("fp64_power_scale_scaled_steps", scale_squarings=6, dynamic_scaling=1)
+        d["seconds_vs_headline"] = d["seconds"] / sec
         run("fp64_identity_power_scale_unscaled_steps", scale_squarings=6)
         d0 = run("fp64_identity_norm_scale_triangle_products")
         out["speedup_vs_fp64_norm_scale"] = d0["seconds"] / sec
@@ -611,7 +619,7 @@ def main():
         # FP64 result; 9 stop near 1e-10 on this matrix (the 1e-10 check fails)
         for sl in (10, 9):
             d = run(f"int8_slices_{sl}_headline_schedule", bulk_dtype=ipr.IPR_FP64_INT8_EMUL,
-                    emul_slices=sl, scale_squarings=6, dynamic_scaling=1,
+                    emul_slices=sl, scale_lanczos=1, dynamic_scaling=1,
                     _dtype_name=f"int8_slices_{sl}")
             d["seconds_vs_headline"] = d["seconds"] / sec
         from paper_1703_02283_amd import train_start

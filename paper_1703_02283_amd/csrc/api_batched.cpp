@@ -155,6 +155,7 @@ int run_batch(const double* dA, double* dC, const std::vector<BatchItem>& items,
   a.bulk_bf16 = s.bulk_dtype == IPR_BF16 ? 1 : 0;
   a.squarings = std::max(0, s.scale_squarings);
   a.dynamic = s.dynamic_scaling ? 1 : 0;
+  a.lanczos_scale = s.scale_lanczos ? 1 : 0;
   if (use_graph) {
     if (int rc = launch_graph(a, grid, stream)) return rc;
   } else {
@@ -208,8 +209,9 @@ int ipr_solve_batched(const double* dA, double* dC, const int64_t* offsets, cons
   if (s.tile != 0 && !valid_tile(s.tile))
     return fail(IPR_EARG, "ipr_solve_batched: tile must be 0, 32 or 64");
   if (s.max_iter < 0) return fail(IPR_EARG, "ipr_solve_batched: max_iter < 0");
-  if (s.scale_lanczos)
-    return fail(IPR_EARG, "ipr_solve_batched: scale_lanczos is an ipr_solve option");
+  if (s.scale_lanczos && s.scale_squarings > 0)
+    return fail(IPR_EARG, "ipr_solve_batched: scale_squarings and scale_lanczos are two ways "
+                "to the same scale: choose one");
   int tiles[IPR_BATCH_BUCKETS];
   ipr_get_batched_tiles(tiles);
   std::vector<BatchItem> items(batch);

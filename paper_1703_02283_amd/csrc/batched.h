@@ -43,6 +43,7 @@ struct BatchArgs {
   int max_iter, bulk_bf16;
   int squarings;  // scale_squarings of the schedule (FP64 items)
   int dynamic;    // dynamic_scaling of the schedule (FP64 items, n >= 32)
+  int lanczos_scale;  // scale_lanczos of the schedule (FP64 items, n >= 32)
 };
 
 hipError_t batched_launch(const BatchArgs& args, int grid, hipStream_t stream);

@@ -424,8 +424,10 @@ struct Bufs {
 // Smallest Ritz value of LZ_STEPS Lanczos steps on the symmetric n x n
 // matrix S (three-term recurrence with one reorthogonalisation against q_j;
 // vec holds 3 n doubles), in every thread: an estimate of lambda_min(S) from
-// above. Called by the whole workgroup.
-__device__ __noinline__ double lanczos_min_wg(const double* S, int n, double* vec, Smem& sm) {
+// above; with hi, the largest Ritz value there too (lambda_max from below).
+// Called by the whole workgroup.
+__device__ __noinline__ double lanczos_min_wg(const double* S, int n, double* vec, Smem& sm,
+                                              double* hi = nullptr) {
   const int tid = threadIdx.x;
   double* qp = vec;          // q_{j-1}
   double* qc = vec + n;      // q_j
@@ -506,9 +508,17 @@ __device__ __noinline__ double lanczos_min_wg(const double* S, int n, double* ve
     beta = bnew;
   }
   __syncthreads();
-  if (tid == 0) sm.bcast[0] = tridiag_min(sm.al, sm.be, m);
+  if (tid == 0) {
+    sm.bcast[0] = tridiag_min(sm.al, sm.be, m);
+    if (hi) {
+      // the largest eigenvalue of T is minus the smallest of -T
+      for (int i = 0; i < m; ++i) sm.al[i] = -sm.al[i];
+      sm.bcast[1] = -tridiag_min(sm.al, sm.be, m);
+    }
+  }
   __syncthreads();
   const double theta = sm.bcast[0];
+  if (hi) *hi = sm.bcast[1];
   __syncthreads();
   return theta;
 }
@@ -582,7 +592,16 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     // sigma (||S_k||_1 ||S_k||_inf)^(1 / 2^(k+1)), stop when the next squaring
     // is predicted to gain less than squaring_worth)
     double sc = sigma;
-    if (args.squarings > 0 && fp64_only) {
+    // or the largest Ritz value of the Lanczos run of the scaled steps, times
+    // 1.01 (an estimate of lambda_max, as in the single solve: no product
+    // spent; the run is made here, before the start, and its smallest Ritz
+    // value serves the scaled steps below)
+    double lz_lo = 0.0;
+    if (args.lanczos_scale && fp64_only && n >= 32) {
+      double hi = 0.0;
+      lz_lo = lanczos_min_wg(b.A, n, b.M[1], sm, &hi);
+      if (hi > 0.0 && isfinite(hi)) sc = fmin(sigma, 1.01 * hi);
+    } else if (args.squarings > 0 && fp64_only) {
       const double worth = squaring_worth(p, args.dynamic && n >= 32);
       const double* src = b.A;
       double prev = sigma;
@@ -622,7 +641,7 @@ __global__ __launch_bounds__(NT, kBatchWgPerCu) void batched_kernel(BatchArgs ar
     double ma = 0.0, mb = 1.0, mu_k = 1.0;
     bool dyn = false;
     if (dyn0) {
-      const double theta = lanczos_min_wg(b.A, n, b.M[1], sm);
+      const double theta = lz_lo > 0.0 ? lz_lo : lanczos_min_wg(b.A, n, b.M[1], sm);
       res.lmin_est = theta;
       if (theta > 0.0 && isfinite(theta)) {
         dyn = true;

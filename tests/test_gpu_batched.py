@@ -221,6 +221,38 @@ def test_tuner_fills_the_table(ipr):
     assert ipr.ipr_get_batched_tiles() == t
 
 
+def test_batched_lanczos_scale(ipr):
+    # the scale from the largest Ritz value of each item's Lanczos run (times
+    # 1.01) inside the persistent kernel: at most 1.01 lambda_max and close to
+    # it, the same roots, fewer iterations than the plain iteration, and the
+    # count of the oracle's scaled iteration from s = 1.01 lambda_max (its own
+    # eigenvalues) within -1..+2
+    ns, ps, mats = _case(200)
+    lams = [np.linalg.eigvalsh(a) for a in mats]
+    buf, offs = _pack(mats)
+    _, r0 = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10)
+    s = ipr.ipr_schedule_default(scale_lanczos=1, dynamic_scaling=1)
+    C, res = ipr.ipr_solve_batched(dev(buf), offs, ns, ps, 1e-10, schedule=s)
+    out = _unpack(host(C), offs, ns)
+    slack = {}
+    for i, (n, p, a, lam) in enumerate(zip(ns, ps, mats, lams)):
+        r = res[i]
+        say("lanczos-scale batch item", i, "n", n, "p", p, "iters", r.iters_fp64,
+            "plain", r0[i].iters_fp64, "scale", r.init_scale, "lmax", lam.max())
+        assert r.status == ipr.IPR_OK, (n, p)
+        assert it.rel_fro(out[i], it.eig_root(a, p)) <= 1e-10, (n, p)
+        assert r.iters_fp64 <= r0[i].iters_fp64, (n, p)
+        if n >= 32:
+            s_ref = 1.01 * lam.max()
+            assert 0.9 * s_ref <= r.init_scale <= s_ref * (1 + 1e-12), (n, p)
+            ref = it.solve(a, p, 1e-10, scaled=s_ref)
+            slack[r.iters_fp64 - ref.iters] = slack.get(r.iters_fp64 - ref.iters, 0) + 1
+            assert ref.status == it.OK and -1 <= r.iters_fp64 - ref.iters <= 2, (n, p)
+        else:
+            assert r.init_scale == pytest.approx(np.sqrt(r.norm1 * r.norminf), rel=1e-15)
+    say("lanczos-scale batch: library minus oracle iterations", sorted(slack.items()))
+
+
 def test_batched_scaled_steps(ipr):
     # the power scale and the scaled steps inside the persistent kernel: same
     # roots, fewer iterations, the oracle's scale, and the count of the

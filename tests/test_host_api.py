@@ -170,7 +170,7 @@ def test_batched_rejects_bad_arguments_before_any_device_call():
     assert rc(bulk_dtype=ipr.IPR_FP16) == ipr.IPR_EARG
     assert rc(tile=48) == ipr.IPR_EARG
     assert rc(max_iter=-1) == ipr.IPR_EARG
-    assert rc(scale_lanczos=1) == ipr.IPR_EARG
+    assert rc(scale_lanczos=1, scale_squarings=6) == ipr.IPR_EARG
     assert rc(n=(ct.c_int * 2)(64, 1025)) == ipr.IPR_EARG
     assert rc(p=(ct.c_int * 2)(0, 2)) == ipr.IPR_EARG and rc(p=(ct.c_int * 2)(2, 9)) == ipr.IPR_EARG
     assert rc(o=(ct.c_int64 * 2)(0, -1)) == ipr.IPR_EARG
