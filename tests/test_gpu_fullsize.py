@@ -1,7 +1,8 @@
 """Parity at the full sizes the bench runs: n = 16384 (p = 2, Householder
 spectrum matrices) and the n = 4096 kernel matrix (p = 1, 2, 3), in the
-bench's launch configuration (default schedule: FP64, identity start,
-triangle products)."""
+bench's launch configuration (FP64, triangle products: the headline's
+Lanczos-scale start with scaled steps, the squaring scale, and the default
+scaled identity)."""
 import json
 import math
 import os
@@ -25,18 +26,21 @@ def ipr():
     return m
 
 
-@pytest.mark.parametrize("headline", [False, True])
+@pytest.mark.parametrize("schedule", ["default", "power", "lanczos"])
 @pytest.mark.parametrize("kappa", [1e4, 1e2])
-def test_householder_16384_p2(ipr, kappa, headline):
-    # headline = the schedule the bench times (power-scale start, scaled
-    # steps); otherwise the default schedule, whose count the oracle fixes
+def test_householder_16384_p2(ipr, kappa, schedule):
+    # lanczos = the schedule the bench times (Lanczos-scale start, scaled
+    # steps); power = the same steps from the certified squaring scale;
+    # default = the plain iteration, whose count the oracle fixes
     import torch
     n, p = 16384, 2
-    say("full size householder n", n, "kappa", kappa, "headline", headline)
+    say("full size householder n", n, "kappa", kappa, "schedule", schedule)
     a, lam = w.householder_spd(n, kappa, seed=0)
     A = dev(a)
     del a
-    kw = dict(scale_squarings=6, dynamic_scaling=1) if headline else {}
+    kw = {"default": {}, "power": dict(scale_squarings=6, dynamic_scaling=1),
+          "lanczos": dict(scale_lanczos=1, dynamic_scaling=1)}[schedule]
+    headline = schedule != "default"
     C, res = ipr.ipr_solve(A, p, 1e-10, schedule=ipr.ipr_schedule_default(**kw))
     say("  status", res.status, "iters", res.iters_fp64, "residual", res.residual_true)
     c = host(C)
@@ -57,8 +61,17 @@ def test_householder_16384_p2(ipr, kappa, headline):
             "iterations golden", gs["scaled"])
         assert res.iters_fp64 < g       # fewer iterations than the plain iteration
         assert abs(res.iters_fp64 - gs["scaled"]) <= 1
-        assert abs(res.init_scale - gs["power_scale"]["scale"]) <= 1e-9 * res.init_scale
-        assert lam.max() <= res.init_scale < math.sqrt(res.norm1 * res.norminf)
+        if schedule == "power":
+            assert abs(res.init_scale - gs["power_scale"]["scale"]) <= 1e-9 * res.init_scale
+            assert lam.max() <= res.init_scale < math.sqrt(res.norm1 * res.norminf)
+        else:
+            # 1.01 times a Ritz value: at most 1.01 lambda_max, and close to
+            # it; the oracle's count from that start on the known spectrum
+            s_ref = 1.01 * lam.max()
+            assert 0.95 * s_ref <= res.init_scale <= s_ref * (1 + 1e-12)
+            k_ref = it.scaled_spectral_count(lam, p, s_ref, 1e-10)[0]
+            say("  oracle count from s = 1.01 lambda_max", k_ref)
+            assert -1 <= res.iters_fp64 - k_ref <= 1
         assert lam.min() * (1 - 1e-12) <= res.lmin_est <= lam.max()
     else:
         assert abs(res.iters_fp64 - g) <= 1
