@@ -53,7 +53,10 @@ def parse():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the kernel-matrix and batched workloads")
+                    help="skip every extra workload (see --sections)")
+    ap.add_argument("--sections", default="all",
+                    help="comma list of the extra workloads to run (kappa1e2, kernel_matrix, "
+                         "storage, sweeps, lowdin, batched, lowp_products); all by default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -169,6 +172,51 @@ def solve_record(ipr, r, seconds, dtype_name=None):
             d["int8_tops"] = ops
             d["int8_frac_of_peak"] = ops / PEAK_INT8_TOPS
     return d
+
+
+def lowp_product_runs(ipr, torch, A, reps=2):
+    """The low-precision products alone on the headline matrix (n = 16384):
+    D = A^T A with bf16, fp16 and fp8 e4m3 operands (full products, per-tile
+    scales, fp32 accumulation) and FP64-accurate from 10 int8 digit slices
+    (triangle products). Host clock per product, operand quantization
+    included; rate against the dtype's dense peak."""
+    n = A.shape[0]
+    D = torch.empty_like(A)
+    out = {"n": n, "reps": reps}
+    cases = (("bf16", ipr.IPR_BF16), ("fp16", ipr.IPR_FP16), ("fp8_e4m3", ipr.IPR_FP8_E4M3),
+             ("int8_slices_10", None))
+    for name, dt in cases:
+        if dt is None:
+            ws = torch.empty(ipr.ipr_gemm_emul_workspace(n, 10), dtype=torch.uint8,
+                             device=A.device)
+            fn = lambda: ipr.ipr_gemm_emul(A, A, 10, out=D, workspace=ws, triangle=True)
+            ops, peak = n * n * (n + 1.0), PEAK_INT8_TOPS   # one FP64-accurate triangle
+        else:
+            ws = torch.empty(ipr.ipr_gemm_lowp_workspace(n), dtype=torch.uint8,
+                             device=A.device)
+            fn = lambda: ipr.ipr_gemm_lowp(A, A, dt, out=D, workspace=ws, triangle=False)
+            ops, peak = 2.0 * n ** 3, PEAK_LP_TFLOPS[name]
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        best = min(times)
+        rec = {"ms_per_product": best * 1e3, "seconds": times}
+        if dt is None:
+            # 55 int8 products of n^3 multiply-adds each make the FP64-accurate triangle
+            rec["fp64_equivalent_tflops"] = ops / best / 1e12
+        else:
+            rec["pflops"] = ops / best / 1e15
+            rec["frac_of_peak"] = ops / best / 1e12 / peak
+        out[name] = rec
+        log(f"lowp product {name}", json.dumps(rec))
+        del ws
+    del D
+    torch.cuda.empty_cache()
+    return out
 
 
 def householder_kappa1e2_runs(ipr, torch, w, dev, tol, p=2, n=16384):
@@ -634,14 +682,26 @@ def main():
             d["seconds_vs_headline"] = d["seconds"] / sec
     out["comparators"] = comps
 
+    wanted = set(args.sections.split(",")) if args.sections != "all" else {
+        "kappa1e2", "kernel_matrix", "storage", "sweeps", "lowdin", "batched", "lowp_products"}
     if not args.no_extra:
-        out["householder_16384_kappa1e2"] = householder_kappa1e2_runs(ipr, torch, w, dev, tol,
-                                                                      p=p, n=n)
-        out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
-        out["storage_sweep_768"] = storage_sweep_runs(ipr, torch, w, dev, tol)
-        out["precision_sweeps_fig2_4"] = precision_sweep_runs(ipr, torch, w, dev)
-        out["lowdin_4096"] = lowdin_runs(ipr, torch, w, dev, tol)
-        out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
+        if "lowp_products" in wanted:
+            out["lowp_products_16384"] = lowp_product_runs(ipr, torch, A)
+        del A, C, ws
+        torch.cuda.empty_cache()
+        if "kappa1e2" in wanted:
+            out["householder_16384_kappa1e2"] = householder_kappa1e2_runs(ipr, torch, w, dev,
+                                                                          tol, p=p, n=n)
+        if "kernel_matrix" in wanted:
+            out["kernel_matrix_4096"] = kernel_matrix_runs(ipr, torch, w, dev, tol)
+        if "storage" in wanted:
+            out["storage_sweep_768"] = storage_sweep_runs(ipr, torch, w, dev, tol)
+        if "sweeps" in wanted:
+            out["precision_sweeps_fig2_4"] = precision_sweep_runs(ipr, torch, w, dev)
+        if "lowdin" in wanted:
+            out["lowdin_4096"] = lowdin_runs(ipr, torch, w, dev, tol)
+        if "batched" in wanted:
+            out["batched_2000"] = batched_runs(ipr, torch, w, dev, tol)
 
     if not args.no_cpu:
         try:
