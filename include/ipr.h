@@ -154,8 +154,9 @@ typedef struct {
                           do not remove it, so the solve restarts in FP64 (fallback_used) and
                           the phase was spent for nothing */
   int scale_lanczos;   /* IDENTITY start, n >= 32: the scale s of C_0 = s^{-1/p} I is 1.01 times
-                          the largest Ritz value of 24 Lanczos steps on A (the run that
-                          dynamic_scaling needs anyway), an estimate of lambda_max from below,
+                          the largest Ritz value of 24 Lanczos steps on A (12 in
+                          ipr_solve_batched; the run that dynamic_scaling needs anyway), an
+                          estimate of lambda_max from below,
                           instead of a certified bound: no product is spent on the scale.
                           Exclusive with scale_squarings (IPR_EARG). Not certified: eq. (2)
                           holds while lambda_max < 2 s, and a diverging run restarts from the
