@@ -56,7 +56,8 @@ def parse():
                     help="skip every extra workload (see --sections)")
     ap.add_argument("--sections", default="all",
                     help="comma list of the extra workloads to run (kappa1e2, kernel_matrix, "
-                         "storage, sweeps, lowdin, batched, lowp_products); all by default")
+                         "storage, sweeps, lowdin, batched, lowp_products, mixed_p1); all by "
+                         "default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -215,6 +216,40 @@ def lowp_product_runs(ipr, torch, A, reps=2):
         log(f"lowp product {name}", json.dumps(rec))
         del ws
     del D
+    torch.cuda.empty_cache()
+    return out
+
+
+def mixed_p1_runs(ipr, torch, w, dev, tol, n=16384, kappa=1e2):
+    """Where a low-precision bulk phase pays: p = 1 (Newton-Schulz order, which
+    removes the bulk phase's non-commuting error) on the n = 16384 Householder
+    matrix at kappa = 1e2 (kappa u_lp < 1 for fp16 and bf16): plain FP64, FP64
+    with the headline's Lanczos scale and scaled steps, and bf16 / fp16 / fp8
+    bulk phases followed by FP64 Newton-Schulz refinement."""
+    a, _ = w.householder_spd(n, kappa, seed=0)
+    A = torch.from_numpy(a).to(dev)
+    del a
+    C = torch.empty_like(A)
+    out = {"workload": f"householder_spd n={n} p=1 kappa={kappa:g} seed=0", "tol": tol}
+    for name, kw, dtn in (
+            ("fp64_identity_norm_scale", {}, None),
+            ("fp64_lanczos_scale_scaled_steps", dict(scale_lanczos=1, dynamic_scaling=1), None),
+            ("bf16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_BF16), "bf16"),
+            ("fp16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP16), "fp16"),
+            ("fp8_e4m3_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP8_E4M3), "fp8_e4m3")):
+        s = ipr.ipr_schedule_default(timing=1, **kw)
+        ipr.ipr_solve(A, 1, tol, schedule=s, out=C)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, r = ipr.ipr_solve(A, 1, tol, schedule=s, out=C)
+        torch.cuda.synchronize()
+        out[name] = solve_record(ipr, r, time.perf_counter() - t, dtn)
+        log(f"p=1 mixed {name}", json.dumps(out[name]))
+    base = out["fp64_identity_norm_scale"]["seconds"]
+    for name in ("fp64_lanczos_scale_scaled_steps", "bf16_bulk_then_fp64",
+                 "fp16_bulk_then_fp64", "fp8_e4m3_bulk_then_fp64"):
+        out[name]["speedup_vs_plain_fp64"] = base / out[name]["seconds"]
+    del A, C
     torch.cuda.empty_cache()
     return out
 
@@ -683,12 +718,15 @@ def main():
     out["comparators"] = comps
 
     wanted = set(args.sections.split(",")) if args.sections != "all" else {
-        "kappa1e2", "kernel_matrix", "storage", "sweeps", "lowdin", "batched", "lowp_products"}
+        "kappa1e2", "kernel_matrix", "storage", "sweeps", "lowdin", "batched", "lowp_products",
+        "mixed_p1"}
     if not args.no_extra:
         if "lowp_products" in wanted:
             out["lowp_products_16384"] = lowp_product_runs(ipr, torch, A)
         del A, C, ws
         torch.cuda.empty_cache()
+        if "mixed_p1" in wanted:
+            out["mixed_p1_16384_kappa1e2"] = mixed_p1_runs(ipr, torch, w, dev, tol, n=n)
         if "kappa1e2" in wanted:
             out["householder_16384_kappa1e2"] = householder_kappa1e2_runs(ipr, torch, w, dev,
                                                                           tol, p=p, n=n)
