@@ -224,8 +224,9 @@ def mixed_p1_runs(ipr, torch, w, dev, tol, n=16384, kappa=1e2):
     """Where a low-precision bulk phase pays: p = 1 (Newton-Schulz order, which
     removes the bulk phase's non-commuting error) on the n = 16384 Householder
     matrix at kappa = 1e2 (kappa u_lp < 1 for fp16 and bf16): plain FP64, FP64
-    with the headline's Lanczos scale and scaled steps, and bf16 / fp16 / fp8
-    bulk phases followed by FP64 Newton-Schulz refinement."""
+    with the headline's Lanczos scale and scaled steps, bf16 / fp16 / fp8 bulk
+    phases followed by FP64 Newton-Schulz refinement, and the bf16 / fp16 bulk
+    phases with scaled steps."""
     a, _ = w.householder_spd(n, kappa, seed=0)
     A = torch.from_numpy(a).to(dev)
     del a
@@ -236,7 +237,11 @@ def mixed_p1_runs(ipr, torch, w, dev, tol, n=16384, kappa=1e2):
             ("fp64_lanczos_scale_scaled_steps", dict(scale_lanczos=1, dynamic_scaling=1), None),
             ("bf16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_BF16), "bf16"),
             ("fp16_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP16), "fp16"),
-            ("fp8_e4m3_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP8_E4M3), "fp8_e4m3")):
+            ("fp8_e4m3_bulk_then_fp64", dict(bulk_dtype=ipr.IPR_FP8_E4M3), "fp8_e4m3"),
+            ("bf16_bulk_scaled_steps_then_fp64",
+             dict(bulk_dtype=ipr.IPR_BF16, scale_lanczos=1, dynamic_scaling=1), "bf16"),
+            ("fp16_bulk_scaled_steps_then_fp64",
+             dict(bulk_dtype=ipr.IPR_FP16, scale_lanczos=1, dynamic_scaling=1), "fp16")):
         s = ipr.ipr_schedule_default(timing=1, **kw)
         ipr.ipr_solve(A, 1, tol, schedule=s, out=C)   # warm-up
         torch.cuda.synchronize()
@@ -247,7 +252,8 @@ def mixed_p1_runs(ipr, torch, w, dev, tol, n=16384, kappa=1e2):
         log(f"p=1 mixed {name}", json.dumps(out[name]))
     base = out["fp64_identity_norm_scale"]["seconds"]
     for name in ("fp64_lanczos_scale_scaled_steps", "bf16_bulk_then_fp64",
-                 "fp16_bulk_then_fp64", "fp8_e4m3_bulk_then_fp64"):
+                 "fp16_bulk_then_fp64", "fp8_e4m3_bulk_then_fp64",
+                 "bf16_bulk_scaled_steps_then_fp64", "fp16_bulk_scaled_steps_then_fp64"):
         out[name]["speedup_vs_plain_fp64"] = base / out[name]["seconds"]
     del A, C
     torch.cuda.empty_cache()

@@ -373,6 +373,9 @@ struct Solver {
   // mu_cur^{1/p} C_k); the product that forms M_{k+1} writes N_{k+1} for
   // mu_next
   double mu_cur = 1.0, mu_next = 1.0;
+  // scaled Newton-Schulz step (p = 1): the step runs on mu C_k, whose
+  // residual is (1 - mu) I + mu R_k, so C_{k+1} = mu (2 - mu) C_k + mu^2 C_k R_k
+  double ns_mu = 1.0;
 
   double* C() { return Cb[ci]; }
   double* M() { return Mb[mi]; }
@@ -449,7 +452,8 @@ struct Solver {
     double* Cn = Cb[ci ^ 1];
     if (ns) {
       Epilogue e;  // C_{k+1} = C_k + C_k R_k (symmetric: C_k - C_k A C_k + C_k)
-      e.beta = 1.0;
+      e.alpha = ns_mu * ns_mu;
+      e.beta = ns_mu * (2.0 - ns_mu);
       e.X = Cc;
       e.D = Cn;
       TRY(prod(Cc, Rns, tri, e));
@@ -1223,6 +1227,23 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
     return status;
   }
   if (lowp) {
+    // Scaled steps in a p = 1 bulk phase: Newton-Schulz steps on mu_k C_k,
+    // mu_k from bounds [ba, bb] on the spectrum of A C_k by the FP64 rules
+    // (the lower end from the Lanczos estimate of lambda_min, the top from
+    // the scale; both narrowed by the residual once it is below 1). The factor
+    // costs no product (it enters the update's epilogue).
+    bool bulk_dyn = s.dynamic_scaling && p == 1 && init == IPR_INIT_IDENTITY && n >= 32 &&
+                    s.evaluation == IPR_EVAL_COUPLED;
+    double ba = 0.0, bb = 1.0;
+    if (bulk_dyn) {
+      double theta = lz_lo;
+      if (!(theta > 0.0))
+        if (int rc = sv.lanczos_min(std::min(24, n - 8), w.m[0], &theta)) return rc;
+      res.lmin_est = theta;
+      ba = std::min(theta / sc, 1.0);
+      bb = sup_phi;
+      bulk_dyn = ba > 0.0 && std::isfinite(ba) && std::isfinite(bb) && bb > 0.0;
+    }
     sv.prod.lowp_dtype = s.bulk_dtype;
     if (p == 1)  // Newton-Schulz bulk: R_0 = I - A C_0
       if (int rc = sv.recompute(true)) return rc;
@@ -1232,6 +1253,17 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       if (int rc = read_scalars(sv.rho_dev(), 1, &rho, stream)) return rc;
       if (!std::isfinite(rho) || rho > 1e6) break;
       if (rho < s.bulk_switch) break;
+      if (bulk_dyn) {
+        if (rho < 1.0) {
+          ba = std::max(ba, 1.0 - rho);
+          bb = std::min(bb, 1.0 + rho);
+        }
+        sv.ns_mu = choose_mu(ba, bb, 1);
+        double na, nb;
+        step_bounds(ba, bb, sv.ns_mu, 1, &na, &nb);
+        ba = na;
+        bb = nb;
+      }
       if (rho < 1.0) {
         if (rho < s.stall_ratio * best) {
           best = rho;
@@ -1248,6 +1280,7 @@ int ipr_solve(const double* dA, double* dC, int n, int p, double tol, const ipr_
       if (int rc = sv.step(p == 1)) return rc;
     }
     sv.prod.lowp_dtype = 0;
+    sv.ns_mu = 1.0;
     res.iters_bulk = kb;
     if (!std::isfinite(rho) || rho > 1e6) {
       // the low-precision phase diverged: start again in FP64 from the scaled identity

@@ -57,6 +57,24 @@ def test_p1_lowp_bulk_then_fp64_newton_schulz_reaches_oracle(ipr, dtype, n):
     assert it.rel_fro(c, ref.c) <= 1e-10
 
 
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_p1_lowp_bulk_with_scaled_steps(ipr, dtype):
+    # scaled Newton-Schulz steps in the bulk phase (factor in the update's
+    # epilogue, chosen from the Lanczos bounds): fewer bulk iterations than
+    # the plain bulk phase, no restart, the same root as the oracle's
+    say("mixed p=1 scaled bulk dtype", dtype)
+    a, _, _ = w.spd_log_spectrum(300, 1e2, seed=60 + dtype)
+    C0, r0 = ipr.ipr_solve(dev(a), 1, 1e-11, schedule=ipr.ipr_schedule_default(bulk_dtype=dtype))
+    s = ipr.ipr_schedule_default(bulk_dtype=dtype, dynamic_scaling=1, scale_lanczos=1)
+    C, res = ipr.ipr_solve(dev(a), 1, 1e-11, schedule=s)
+    say("  bulk iterations", res.iters_bulk, "plain bulk", r0.iters_bulk, "fp64", res.iters_fp64)
+    assert res.status == ipr.IPR_OK and res.fallback_used == 0, res.as_dict()
+    assert 0 < res.iters_bulk < r0.iters_bulk
+    ref = it.solve(a, 1, 1e-11, evaluation="newton_schulz")
+    assert it.rel_fro(host(C), ref.c) <= 1e-10
+    assert it.rel_fro(host(C), it.eig_root(a, 1)) <= 1e-10
+
+
 def test_p1_bf16_bulk_on_kernel_matrix(ipr):
     a = w.kernel_matrix(512, seed=3)
     s = ipr.ipr_schedule_default(bulk_dtype=1)
