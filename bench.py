@@ -40,6 +40,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+SECTIONS = ("lowp_products", "mixed_p1", "kappa1e2", "kernel_matrix", "storage", "sweeps",
+            "lowdin", "batched")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,7 +64,11 @@ def parse():
                          "default")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    unknown = set(args.sections.split(",")) - set(SECTIONS) if args.sections != "all" else set()
+    if unknown:
+        ap.error(f"unknown sections {sorted(unknown)}; known: {', '.join(SECTIONS)}")
+    return args
 
 
 def kernel_source_hash():
@@ -723,9 +731,7 @@ def main():
             d["seconds_vs_headline"] = d["seconds"] / sec
     out["comparators"] = comps
 
-    wanted = set(args.sections.split(",")) if args.sections != "all" else {
-        "kappa1e2", "kernel_matrix", "storage", "sweeps", "lowdin", "batched", "lowp_products",
-        "mixed_p1"}
+    wanted = set(args.sections.split(",")) if args.sections != "all" else set(SECTIONS)
     if not args.no_extra:
         if "lowp_products" in wanted:
             out["lowp_products_16384"] = lowp_product_runs(ipr, torch, A)
