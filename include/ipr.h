@@ -118,9 +118,10 @@ typedef struct {
   int scale_squarings; /* IDENTITY start: up to this many repeated squarings of A / sigma tighten
                           the scale s of C_0 = s^{-1/p} I (default 0: s = sigma, the norm bound
                           of eq. (3)); see ipr_solve */
-  int dynamic_scaling; /* IDENTITY start, FP64: scale every step by a factor chosen from bounds on
-                          the spectrum of M_k, with the lower end estimated by Lanczos (default 0:
-                          the plain iteration of eq. (1)); see ipr_solve */
+  int dynamic_scaling; /* IDENTITY start, FP64 (and the Newton-Schulz steps of a p = 1
+                          low-precision bulk phase): scale every step by a factor chosen from
+                          bounds on the spectrum of M_k, with the lower end estimated by Lanczos
+                          (default 0: the plain iteration of eq. (1)); see ipr_solve */
   int evaluation;      /* ipr_evaluation (default COUPLED); LITERAL and NEWTON_SCHULZ need the FP64
                           bulk dtype and ipr_solve (not the batched solver) */
   int emul_slices;     /* IPR_FP64_INT8_EMUL: 7-bit digits per operand, 1..12 (0: 10, which
