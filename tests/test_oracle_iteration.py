@@ -230,3 +230,22 @@ def test_householder_root_is_the_definition():
         assert np.linalg.norm(np.eye(300) - np.linalg.matrix_power(x, p) @ a) < 1e-10
     a64, _ = w.householder_spd(256, 1e2, seed=9)
     assert it.rel_fro(it.householder_root(256, 1e2, 9, 2), it.eig_root(a64, 2)) < 1e-12
+
+
+def test_scaled_newton_schulz_step_identity():
+    # A Newton-Schulz step on mu C (residual (1 - mu) I + mu R, R = I - A C)
+    # equals mu (2 - mu) C + mu^2 C R: the coefficients the p = 1 bulk phase's
+    # scaled steps put into the update's epilogue. On the spectrum it is
+    # m -> g(mu m), g(m) = m (2 - m), the coupled map for p = 1.
+    a, lam, q = _spd(40, 1e3, 21)
+    c = it.eig_root(a, 1) @ (np.eye(40) + 0.1 * a / lam.max())   # a polynomial in A
+    r = np.eye(40) - a @ c
+    for mu in (1.0, 1.3, 1.7):
+        cs = mu * c
+        direct = cs + cs @ (np.eye(40) - a @ cs)
+        formula = mu * (2.0 - mu) * c + mu * mu * (c @ r)
+        assert np.max(np.abs(direct - formula)) <= 1e-12 * np.max(np.abs(direct))
+        m = np.sort(np.linalg.eigvals(a @ c).real)
+        m1 = np.sort(np.linalg.eigvals(a @ formula).real)
+        assert np.allclose(m1, np.sort(it.residual_map(1.0 - mu * m, 1) * -1.0 + 1.0),
+                           rtol=0, atol=1e-10)
